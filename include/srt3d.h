@@ -1,0 +1,216 @@
+/*
+ * srt3d.h -- C ABI of the sketched RT3D (SRT3D) library for AMD Instinct MI355X (gfx950).
+ *
+ * Paper: J. Tachella, M. P. Sheehan, M. E. Davies, "Sketched RT3D: How to reconstruct
+ * billions of photons per second", ICASSP 2022 (arXiv 2203.00952).
+ *
+ * Conventions shared by every entry point
+ *  - A pointer named d_* is a device pointer owned by the caller.  The library never
+ *    allocates device memory; scratch space comes from a caller-provided workspace whose
+ *    size is returned by the matching *_workspace_bytes query.  A pointer named h_* is a
+ *    host pointer.
+ *  - Every call is asynchronous on the HIP stream passed as `stream` (a hipStream_t cast to
+ *    void*, NULL = the null stream).  Argument errors are detected on the host and returned
+ *    before anything is enqueued.  A HIP launch failure returns SRT3D_EDEVICE.
+ *  - Data-dependent problems are counted on the device into an optional int32 d_err[2]
+ *    (may be NULL) that the caller zeroes and reads after synchronising:
+ *      d_err[0] += number of stamps outside [0, T) (folded by the mathematical modulus),
+ *      d_err[1] += number of pixels whose offsets decrease (treated as empty).
+ *  - The library keeps no global mutable state; concurrent calls on different streams with
+ *    disjoint outputs and workspaces are safe.
+ *  - Layouts: a sketch is float32 [P][m][2] (real, imaginary interleaved, harmonic l = 1..m
+ *    at index l-1), i.e. complex64 [P][m]; pixels are row-major (p = i * cols + j).
+ */
+#ifndef SRT3D_H
+#define SRT3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SRT3D_VERSION 1
+
+enum srt3d_status {
+    SRT3D_OK = 0,
+    SRT3D_EINVAL = -1,   /* invalid argument (sizes, NULL pointers, parameters) */
+    SRT3D_ENOMEM = -2,   /* workspace smaller than the matching *_workspace_bytes */
+    SRT3D_EDEVICE = -3   /* a HIP call failed */
+};
+
+/* Arithmetic of the histogram sketch (srt3d_sketch_from_hist). */
+enum srt3d_precision {
+    SRT3D_PREC_FP32 = 0,   /* FP32 counts x FP32 DFT matrix, FP32 accumulation */
+    SRT3D_PREC_FP16X2 = 1, /* counts split exactly into FP16 hi/lo, DFT matrix as a sum of 2 FP16 */
+    SRT3D_PREC_BF16X3 = 2  /* counts split exactly into BF16 hi/lo, DFT matrix as a sum of 3 BF16 */
+};
+
+/* One stage of an SRT3D iteration (srt3d_step). */
+enum srt3d_stage {
+    SRT3D_STAGE_DATA = 0,      /* gradient step on depth then intensity, projection */
+    SRT3D_STAGE_DEPTH = 1,     /* point-cloud (depth) denoiser */
+    SRT3D_STAGE_INTENSITY = 2  /* intensity denoiser and point removal */
+};
+
+/* Limits of the reconstruction kernels. */
+#define SRT3D_MAX_M_RECON 64   /* harmonics usable by init/iterate */
+#define SRT3D_MAX_K 3          /* surfaces per pixel */
+#define SRT3D_MAX_R 3          /* denoiser window radius */
+#define SRT3D_NSCAL 8          /* floats in srt3d_state.scal */
+
+/*
+ * Reconstruction parameters.  Section 3 fixes the data term (eq. 8 with W = I); the
+ * initialisation, step sizes, denoisers and thresholds are left open by the paper and are
+ * exposed here.  Fill with srt3d_params_default and override fields as needed.
+ */
+typedef struct srt3d_params {
+    int32_t rows, cols;   /* frame size in pixels; P = rows * cols */
+    int32_t T;            /* number of time bins; stamps live in [0, T) */
+    int32_t m;            /* harmonics l = 1..m, w_l = 2 pi l / T */
+    int32_t K_max;        /* surfaces per pixel, 1..SRT3D_MAX_K */
+    int32_t iters;        /* iterations run by srt3d_reconstruct */
+    int32_t R;            /* denoiser window radius (default 2) */
+    int32_t Rb;           /* background box-filter radius (default 1) */
+    int32_t init_stride;  /* grid step of the initial search; 0 = max(1, T / (8 m)) */
+    float eta_t;          /* depth step scale (default 1) */
+    float eta_a;          /* intensity step scale (default 1) */
+    float lambda_z;       /* depth-denoiser relaxation (default 1) */
+    float tau_z;          /* depth gate in bins; <= 0 = 3 x std of the impulse response */
+    float r_min;          /* photons below which a point is removed (default 1) */
+} srt3d_params;
+
+/*
+ * Reconstruction state, all arrays caller-allocated on the device.
+ *   t[b], alpha[b], active[b] : b = 0, 1 ping-pong halves, each [P][K_max] (point p*K_max + k)
+ *   hhat  : float32 [m][2], spectrum of the impulse response (written by srt3d_init)
+ *   scal  : float32 [SRT3D_NSCAL]: [0] max photon count n_max, [1] gamma_t, [2] gamma_alpha,
+ *           [3] depth gate tau_z (all written by srt3d_init)
+ *   cur   : index of the half that holds the current state; every call that advances the
+ *           state updates it on the host (the value is known at enqueue time).
+ * t is in bins on [0, T), alpha is the probability of each surface (eq. 1), active is 0/1.
+ */
+typedef struct srt3d_state {
+    float* t[2];
+    float* alpha[2];
+    uint8_t* active[2];
+    float* hhat;
+    float* scal;
+    int32_t cur;
+} srt3d_state;
+
+/* Defaults for the fields the paper leaves open (see srt3d_params). */
+void srt3d_params_default(srt3d_params* p, int32_t rows, int32_t cols, int32_t T, int32_t m,
+                          int32_t K_max);
+
+/* ---------------------------------------------------------------------------------------
+ * Phase table -- the frequencies of Section 2, w_l = 2 pi l / T, evaluated at integer phases:
+ *     d_table[k] = (cos, sin)(2 pi k / T), k = 0..T-1, FP64 values rounded to FP32.
+ * Build it once per T and pass it to every srt3d_sketch call with that T.
+ *   d_table float32 [T][2], 8-byte aligned.  Constraints: 2 <= T, T * 8 <= 65536.
+ * ------------------------------------------------------------------------------------- */
+int srt3d_phase_table(int32_t T, float* d_table, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Sketch of photon time stamps -- Section 2, eq. (3):
+ *     z_l = (1/n) sum_p exp(i w_l x_p),  w_l = 2 pi l / T,  l = 1..m.
+ * The phase w_l x_p is reduced exactly as the integer k = (l x_p) mod T and looked up in the
+ * phase table; partial sums are FP32 and the division by n is FP64.  One kernel launch.
+ *   d_stamps  int32 [N] time stamps, pixel-major (CSR); stamps outside [0, T) are folded
+ *             mod T and counted in d_err[0]
+ *   N         number of stamps in d_stamps; offsets are clamped to [0, N] before use
+ *             (a clamped pixel is counted in d_err[1])
+ *   d_offsets int64 [P + 1] pixel p owns stamps [offsets[p], offsets[p+1]); a decreasing pair
+ *             makes the pixel empty and is counted in d_err[1]
+ *   d_table   float32 [T][2] built by srt3d_phase_table(T)
+ *   d_z       float32 [P][m][2] output sketch (8-byte aligned); z = 0 for a pixel with n = 0
+ *   d_n       int32 [P] output photon count (of this call, or the accumulated count)
+ *   d_acc, d_nacc  optional long-exposure accumulators (both NULL or both set):
+ *             double [P][m][2] running sums S_l and int64 [P] running counts; the call adds
+ *             this batch (the sketch is updated online with each photon, Section 2) and
+ *             writes z = acc / nacc (FP64 division rounded to FP32) and n = min(nacc, INT32_MAX).
+ *             The caller zeroes them at the start of an exposure.
+ * Constraints: P >= 1, N >= 0, 2 <= T, 1 <= m, m <= T/2 (higher harmonics are conjugates of
+ * lower ones), (int64) m * T < 2^31, T * 8 <= 65536 (the table lives in LDS).
+ * ------------------------------------------------------------------------------------- */
+int srt3d_sketch(const int32_t* d_stamps, int64_t N, const int64_t* d_offsets, int32_t P,
+                 int32_t T, int32_t m, const float* d_table, float* d_z, int32_t* d_n,
+                 double* d_acc, int64_t* d_nacc, int32_t* d_err, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Sketch of per-pixel ToA histograms -- eq. (2) with unit bins [t, t+1), then eq. (3):
+ *     S_l = sum_t H[p][t] exp(i w_l t),  n = sum_t H[p][t],  z = S / n,
+ * computed as the product H [P x T] . F [T x 2m] with F the cos/sin DFT columns.
+ * srt3d_hist_prepare writes F (split for the chosen precision) into d_ws, of
+ * srt3d_hist_workspace_bytes(T, m, precision) bytes; build it once per (T, m, precision).
+ * srt3d_sketch_from_hist is then one kernel launch:
+ *   d_hist    uint16 [P][T] row-major counts, 16-byte aligned
+ *   precision srt3d_precision: FP32 (FP32 matrix cores), FP16X2 or BF16X3 (16-bit matrix
+ *             cores on exact hi/lo splits of the counts and a 2- or 3-term split of F,
+ *             FP32 accumulation)
+ *   d_ws      the prepared F
+ *   d_z, d_n  as in srt3d_sketch (n is exact)
+ * Constraints: P >= 1, 2 <= T, 1 <= m <= 32, m <= T/2, T % 32 == 0, d_ws 16-byte aligned.
+ * ------------------------------------------------------------------------------------- */
+size_t srt3d_hist_workspace_bytes(int32_t T, int32_t m, int32_t precision);
+int srt3d_hist_prepare(int32_t T, int32_t m, int32_t precision, void* d_ws, size_t ws_bytes,
+                       void* stream);
+int srt3d_sketch_from_hist(const uint16_t* d_hist, int32_t P, int32_t T, int32_t m,
+                           int32_t precision, const void* d_ws, size_t ws_bytes, float* d_z,
+                           int32_t* d_n, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * SRT3D reconstruction -- Section 3, eq. (8) with W = I (the sketched loss
+ * n ||z - Phi(theta)||^2, Phi_l = hhat_l sum_k alpha_k exp(i w_l t_k), eq. 4), alternated
+ * with point-cloud and intensity denoising as in RT3D.
+ *
+ * srt3d_init: computes hhat from the impulse response, the frame's n_max and step sizes,
+ * and the initial points (greedy sketched matched filter on the grid 0, s, 2s, ...).
+ *   d_z, d_n   sketch and counts of the frame ([P][m][2], [P]); P = rows * cols
+ *   d_irf      double [irf_len] impulse response h on lags i - irf_origin (device memory)
+ *   st         state whose arrays are allocated for p->rows, p->cols, p->m, p->K_max;
+ *              st->cur is set to 0
+ *   d_ws       workspace of srt3d_init_workspace_bytes(p) bytes
+ * srt3d_step:    runs one stage (srt3d_stage) on the current state.
+ * srt3d_iterate: runs `iters` full iterations (data, depth, intensity).
+ * srt3d_finalize: background b = n max(0, 1 - sum alpha) / T (box filtered) and the output
+ *   points per pixel sorted by depth with inactive slots last:
+ *   d_depth, d_intensity float32 [P][K_max] (bins; photons n alpha), d_active uint8 [P][K_max],
+ *   d_bg float32 [P] (photons per bin).  Any output pointer may be NULL to skip it.
+ * srt3d_reconstruct: init + iterate(p->iters) + finalize.
+ * Constraints: rows, cols >= 1, 1 <= m <= SRT3D_MAX_M_RECON, m <= T/2, T * 8 <= 65536,
+ * 1 <= K_max <= SRT3D_MAX_K, 0 <= R <= SRT3D_MAX_R, 0 <= Rb <= 8, irf_len >= 1,
+ * 0 <= irf_origin < irf_len, iters >= 0, eta_t, eta_a >= 0.
+ * ------------------------------------------------------------------------------------- */
+size_t srt3d_init_workspace_bytes(const srt3d_params* p);
+int srt3d_init(const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len,
+               int32_t irf_origin, const srt3d_params* p, srt3d_state* st, void* d_ws,
+               size_t ws_bytes, void* stream);
+int srt3d_step(srt3d_state* st, const float* d_z, const int32_t* d_n, const srt3d_params* p,
+               int32_t stage, void* stream);
+int srt3d_iterate(srt3d_state* st, const float* d_z, const int32_t* d_n,
+                  const srt3d_params* p, int32_t iters, void* stream);
+int srt3d_finalize(const srt3d_state* st, const int32_t* d_n, const srt3d_params* p,
+                   float* d_depth, float* d_intensity, uint8_t* d_active, float* d_bg,
+                   void* stream);
+int srt3d_reconstruct(const float* d_z, const int32_t* d_n, const double* d_irf,
+                      int32_t irf_len, int32_t irf_origin, const srt3d_params* p,
+                      srt3d_state* st, float* d_depth, float* d_intensity, uint8_t* d_active,
+                      float* d_bg, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Inspection entry point used to check the exact part of the sketch.
+ * srt3d_phase_indices: d_k[(l-1) * N + p] = (l * x_p) mod T (mathematical modulus) for
+ *   l = 1..m, the integer phase the sketch kernels use; d_x int32 [N], d_k int32 [m * N].
+ * ------------------------------------------------------------------------------------- */
+int srt3d_phase_indices(const int32_t* d_x, int64_t N, int32_t T, int32_t m, int32_t* d_k,
+                        void* stream);
+
+const char* srt3d_strerror(int status);
+int srt3d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SRT3D_H */

@@ -1,0 +1,325 @@
+"""ctypes binding of libsrt3d.so (the C ABI declared in include/srt3d.h).
+
+Argument marshalling only: tensors are checked for device, dtype and layout, outputs and
+workspaces are allocated with torch on the caller's device, and every call is enqueued on
+torch's current HIP stream.  All arithmetic runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, fields
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsrt3d.so")
+
+SRT3D_OK, SRT3D_EINVAL, SRT3D_ENOMEM, SRT3D_EDEVICE = 0, -1, -2, -3
+PRECISIONS = {"fp32": 0, "fp16x2": 1, "bf16x3": 2}
+STAGES = {"data": 0, "depth": 1, "intensity": 2}
+MAX_M_RECON, MAX_K, MAX_R, NSCAL = 64, 3, 3, 8
+
+
+class SRT3DError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {_lib().srt3d_strerror(status).decode()} ({status})")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("cols", ctypes.c_int32), ("T", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("K_max", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("R", ctypes.c_int32), ("Rb", ctypes.c_int32), ("init_stride", ctypes.c_int32),
+                ("eta_t", ctypes.c_float), ("eta_a", ctypes.c_float), ("lambda_z", ctypes.c_float),
+                ("tau_z", ctypes.c_float), ("r_min", ctypes.c_float)]
+
+
+class _State(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_void_p * 2), ("alpha", ctypes.c_void_p * 2), ("active", ctypes.c_void_p * 2),
+                ("hhat", ctypes.c_void_p), ("scal", ctypes.c_void_p), ("cur", ctypes.c_int32)]
+
+
+_VP, _I32, _I64, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+_SIGS = {
+    "srt3d_params_default": (None, [ctypes.POINTER(_Params), _I32, _I32, _I32, _I32, _I32]),
+    "srt3d_phase_table": (_I32, [_I32, _VP, _VP]),
+    "srt3d_sketch": (_I32, [_VP, _I64, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "srt3d_hist_workspace_bytes": (_SZ, [_I32, _I32, _I32]),
+    "srt3d_hist_prepare": (_I32, [_I32, _I32, _I32, _VP, _SZ, _VP]),
+    "srt3d_sketch_from_hist": (_I32, [_VP, _I32, _I32, _I32, _I32, _VP, _SZ, _VP, _VP, _VP]),
+    "srt3d_init_workspace_bytes": (_SZ, [ctypes.POINTER(_Params)]),
+    "srt3d_init": (_I32, [_VP, _VP, _VP, _I32, _I32, ctypes.POINTER(_Params), ctypes.POINTER(_State), _VP, _SZ,
+                          _VP]),
+    "srt3d_step": (_I32, [ctypes.POINTER(_State), _VP, _VP, ctypes.POINTER(_Params), _I32, _VP]),
+    "srt3d_iterate": (_I32, [ctypes.POINTER(_State), _VP, _VP, ctypes.POINTER(_Params), _I32, _VP]),
+    "srt3d_finalize": (_I32, [ctypes.POINTER(_State), _VP, ctypes.POINTER(_Params), _VP, _VP, _VP, _VP, _VP]),
+    "srt3d_reconstruct": (_I32, [_VP, _VP, _VP, _I32, _I32, ctypes.POINTER(_Params), ctypes.POINTER(_State),
+                                 _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "srt3d_phase_indices": (_I32, [_VP, _I64, _I32, _I32, _VP, _VP]),
+    "srt3d_strerror": (ctypes.c_char_p, [_I32]),
+    "srt3d_version": (_I32, []),
+}
+EXPORTS = tuple(_SIGS)
+
+_LIB = None
+
+
+def _lib():
+    """Load libsrt3d.so; raise if it has not been built (there is no fallback path)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2203_00952_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _check(status: int, what: str):
+    if status == SRT3D_EINVAL:
+        raise ValueError(f"{what}: invalid argument")
+    if status != SRT3D_OK:
+        raise SRT3DError(status, what)
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() else ctypes.c_void_p(0)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0) if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# ----------------------------------------------------------------------------- sketches
+_TABLES: dict = {}
+_DFT: dict = {}
+
+
+def phase_table(T: int, device="cuda") -> torch.Tensor:
+    """Build the float32 [T, 2] phase table (cos, sin)(2 pi k / T) on `device`."""
+    tab = torch.empty((T, 2), dtype=torch.float32, device=device)
+    _check(_lib().srt3d_phase_table(T, _ptr(tab), _stream(tab.device)), "srt3d_phase_table")
+    return tab
+
+
+def cached_phase_table(T: int, device) -> torch.Tensor:
+    device = torch.device(device)
+    key = (device.index if device.index is not None else torch.cuda.current_device(), T)
+    if key not in _TABLES:
+        _TABLES[key] = phase_table(T, device)
+        torch.cuda.current_stream(device).synchronize()   # usable from any stream afterwards
+    return _TABLES[key]
+
+
+def sketch(stamps: torch.Tensor, offsets: torch.Tensor, T: int, m: int, *, acc=None, nacc=None, err=None,
+           z=None, n=None, table=None):
+    """Photon sketch (eq. 3).  Returns (z float32 [P, m, 2], n int32 [P])."""
+    P = offsets.numel() - 1
+    dev = offsets.device
+    ps = _dev(stamps, torch.int32, "stamps")
+    po = _dev(offsets, torch.int64, "offsets")
+    z = torch.empty((P, m, 2), dtype=torch.float32, device=dev) if z is None else z
+    n = torch.empty(P, dtype=torch.int32, device=dev) if n is None else n
+    if acc is not None:
+        _dev(acc, torch.float64, "acc")
+        _dev(nacc, torch.int64, "nacc")
+    if err is not None:
+        _dev(err, torch.int32, "err")
+    if table is None:
+        if not (2 <= T and T * 8 <= 65536):
+            raise ValueError("sketch: invalid T")
+        table = cached_phase_table(T, dev)
+    _check(_lib().srt3d_sketch(ps, stamps.numel(), po, P, T, m, _dev(table, torch.float32, "table"),
+                               _dev(z, torch.float32, "z"), _dev(n, torch.int32, "n"), _ptr(acc), _ptr(nacc),
+                               _ptr(err), _stream(dev)), "srt3d_sketch")
+    return z, n
+
+
+def hist_workspace(T: int, m: int, precision: str, device) -> torch.Tensor:
+    """The prepared DFT matrix for (T, m, precision) on `device` (built once, then cached)."""
+    device = torch.device(device)
+    prec = PRECISIONS[precision]
+    key = (device.index if device.index is not None else torch.cuda.current_device(), T, m, prec)
+    if key not in _DFT:
+        nbytes = _lib().srt3d_hist_workspace_bytes(T, m, prec)
+        if nbytes == 0:
+            raise ValueError("sketch_from_hist: invalid T, m or precision")
+        ws = _workspace(nbytes, device)
+        _check(_lib().srt3d_hist_prepare(T, m, prec, _ptr(ws), ws.numel(), _stream(device)), "srt3d_hist_prepare")
+        torch.cuda.current_stream(device).synchronize()
+        _DFT[key] = ws
+    return _DFT[key]
+
+
+def sketch_from_hist(hist: torch.Tensor, m: int, precision: str = "fp32", *, z=None, n=None, workspace=None):
+    """Histogram sketch (eq. 2 then eq. 3); `hist` holds uint16 counts as int16 or uint16 [P, T]."""
+    if hist.dim() != 2:
+        raise ValueError("hist must be [P, T]")
+    P, T = hist.shape
+    dev = hist.device
+    if hist.dtype not in (torch.int16, torch.uint16):
+        raise TypeError("hist must be int16 (uint16 bits) or uint16")
+    ph = _dev(hist, hist.dtype, "hist")
+    prec = PRECISIONS[precision]
+    z = torch.empty((P, m, 2), dtype=torch.float32, device=dev) if z is None else z
+    n = torch.empty(P, dtype=torch.int32, device=dev) if n is None else n
+    ws = hist_workspace(T, m, precision, dev) if workspace is None else workspace
+    _check(_lib().srt3d_sketch_from_hist(ph, P, T, m, prec, _ptr(ws), ws.numel(), _dev(z, torch.float32, "z"),
+                                         _dev(n, torch.int32, "n"), _stream(dev)), "srt3d_sketch_from_hist")
+    return z, n
+
+
+def phase_indices(x: torch.Tensor, T: int, m: int) -> torch.Tensor:
+    k = torch.empty((m, x.numel()), dtype=torch.int32, device=x.device)
+    _check(_lib().srt3d_phase_indices(_dev(x, torch.int32, "x"), x.numel(), T, m, _ptr(k), _stream(x.device)),
+           "srt3d_phase_indices")
+    return k
+
+
+# ----------------------------------------------------------------------------- reconstruction
+@dataclass
+class Params:
+    rows: int
+    cols: int
+    T: int
+    m: int
+    K_max: int = 1
+    iters: int = 50
+    R: int = 2
+    Rb: int = 1
+    init_stride: int = 0
+    eta_t: float = 1.0
+    eta_a: float = 1.0
+    lambda_z: float = 1.0
+    tau_z: float = 0.0
+    r_min: float = 1.0
+
+    @classmethod
+    def default(cls, rows, cols, T, m, K_max=1, **kw) -> "Params":
+        c = _Params()
+        _lib().srt3d_params_default(ctypes.byref(c), rows, cols, T, m, K_max)
+        base = {f.name: getattr(c, f.name) for f in fields(cls)}
+        base.update(kw)
+        return cls(**base)
+
+    def c(self) -> _Params:
+        return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
+
+    @property
+    def P(self) -> int:
+        return self.rows * self.cols
+
+
+class Reconstructor:
+    """Device-resident SRT3D state for one frame geometry, with its workspace."""
+
+    def __init__(self, params: Params, device="cuda"):
+        self.p = params
+        self.device = torch.device(device)
+        PK = params.P * params.K_max
+        self.t = torch.zeros((2, PK), dtype=torch.float32, device=self.device)
+        self.alpha = torch.zeros((2, PK), dtype=torch.float32, device=self.device)
+        self.active = torch.zeros((2, PK), dtype=torch.uint8, device=self.device)
+        self.hhat = torch.zeros((params.m, 2), dtype=torch.float32, device=self.device)
+        self.scal = torch.zeros(NSCAL, dtype=torch.float32, device=self.device)
+        self._cp = params.c()
+        ws = _lib().srt3d_init_workspace_bytes(ctypes.byref(self._cp))
+        if ws == 0:
+            raise ValueError(f"invalid reconstruction parameters {params}")
+        self.ws = _workspace(ws, self.device)
+        self._st = _State()
+        for b in range(2):
+            self._st.t[b] = self.t[b].data_ptr()
+            self._st.alpha[b] = self.alpha[b].data_ptr()
+            self._st.active[b] = self.active[b].data_ptr()
+        self._st.hhat = self.hhat.data_ptr()
+        self._st.scal = self.scal.data_ptr()
+        self._st.cur = 0
+
+    @property
+    def cur(self) -> int:
+        return self._st.cur
+
+    def _zn(self, z, n):
+        if z is not None:
+            if tuple(z.shape) != (self.p.P, self.p.m, 2):
+                raise ValueError("z must be [P, m, 2]")
+            _dev(z, torch.float32, "z")
+        if tuple(n.shape) != (self.p.P,):
+            raise ValueError("n must be [P]")
+        _dev(n, torch.int32, "n")
+
+    def init(self, z, n, irf: torch.Tensor, origin: int):
+        self._zn(z, n)
+        _dev(irf, torch.float64, "irf")
+        _check(_lib().srt3d_init(_ptr(z), _ptr(n), _ptr(irf), irf.numel(), origin, ctypes.byref(self._cp),
+                                 ctypes.byref(self._st), _ptr(self.ws), self.ws.numel(), _stream(self.device)),
+               "srt3d_init")
+
+    def step(self, stage: str, z, n):
+        self._zn(z, n)
+        _check(_lib().srt3d_step(ctypes.byref(self._st), _ptr(z), _ptr(n), ctypes.byref(self._cp), STAGES[stage],
+                                 _stream(self.device)), "srt3d_step")
+
+    def iterate(self, z, n, iters: int):
+        self._zn(z, n)
+        _check(_lib().srt3d_iterate(ctypes.byref(self._st), _ptr(z), _ptr(n), ctypes.byref(self._cp), iters,
+                                    _stream(self.device)), "srt3d_iterate")
+
+    def finalize(self, n):
+        P, K = self.p.P, self.p.K_max
+        out = dict(depth=torch.empty((P, K), dtype=torch.float32, device=self.device),
+                   intensity=torch.empty((P, K), dtype=torch.float32, device=self.device),
+                   active=torch.empty((P, K), dtype=torch.uint8, device=self.device),
+                   bg=torch.empty(P, dtype=torch.float32, device=self.device))
+        self._zn(None, n)
+        _check(_lib().srt3d_finalize(ctypes.byref(self._st), _ptr(n), ctypes.byref(self._cp), _ptr(out["depth"]),
+                                     _ptr(out["intensity"]), _ptr(out["active"]), _ptr(out["bg"]),
+                                     _stream(self.device)), "srt3d_finalize")
+        return out
+
+    def reconstruct(self, z, n, irf, origin: int, out=None):
+        self._zn(z, n)
+        _dev(irf, torch.float64, "irf")
+        P, K = self.p.P, self.p.K_max
+        if out is None:
+            out = dict(depth=torch.empty((P, K), dtype=torch.float32, device=self.device),
+                       intensity=torch.empty((P, K), dtype=torch.float32, device=self.device),
+                       active=torch.empty((P, K), dtype=torch.uint8, device=self.device),
+                       bg=torch.empty(P, dtype=torch.float32, device=self.device))
+        _check(_lib().srt3d_reconstruct(_ptr(z), _ptr(n), _ptr(irf), irf.numel(), origin, ctypes.byref(self._cp),
+                                        ctypes.byref(self._st), _ptr(out["depth"]), _ptr(out["intensity"]),
+                                        _ptr(out["active"]), _ptr(out["bg"]), _ptr(self.ws), self.ws.numel(),
+                                        _stream(self.device)), "srt3d_reconstruct")
+        return out
+
+    def state(self):
+        """(t, alpha, active) of the current half, shaped [P, K_max]."""
+        c, P, K = self.cur, self.p.P, self.p.K_max
+        return (self.t[c].view(P, K), self.alpha[c].view(P, K), self.active[c].view(P, K))
+
+    def set_state(self, t, alpha, active):
+        """Overwrite the current state (e.g. to start from an externally computed initialisation)."""
+        c, P, K = self.cur, self.p.P, self.p.K_max
+        self.t[c].view(P, K).copy_(torch.as_tensor(t, dtype=torch.float32).reshape(P, K))
+        self.alpha[c].view(P, K).copy_(torch.as_tensor(alpha, dtype=torch.float32).reshape(P, K))
+        self.active[c].view(P, K).copy_(torch.as_tensor(active, dtype=torch.uint8).reshape(P, K))

@@ -1,0 +1,189 @@
+// C ABI of libsrt3d: argument validation, workspace carving and launch order.
+#include <climits>
+#include <cstring>
+
+#include "common.hpp"
+
+using namespace srt3d;
+
+namespace {
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+inline int dev_status(hipError_t e) { return e == hipSuccess ? SRT3D_OK : SRT3D_EDEVICE; }
+inline bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+bool sketch_dims_ok(int32_t T, int32_t m) {
+    return T >= 2 && m >= 1 && m <= T / 2 && (int64_t)m * T < (1LL << 31) && (int64_t)T * 8 <= 65536;
+}
+
+int check_params(const srt3d_params* p) {
+    if (!p) return SRT3D_EINVAL;
+    if (p->rows < 1 || p->cols < 1 || (int64_t)p->rows * p->cols > INT_MAX) return SRT3D_EINVAL;
+    if (!sketch_dims_ok(p->T, p->m) || p->m > SRT3D_MAX_M_RECON) return SRT3D_EINVAL;
+    if (p->K_max < 1 || p->K_max > SRT3D_MAX_K) return SRT3D_EINVAL;
+    if (p->R < 0 || p->R > SRT3D_MAX_R || p->Rb < 0 || p->Rb > 8) return SRT3D_EINVAL;
+    if (p->iters < 0 || p->init_stride < 0 || p->init_stride >= p->T) return SRT3D_EINVAL;
+    if (!(p->eta_t >= 0.f) || !(p->eta_a >= 0.f) || !(p->lambda_z >= 0.f) || !(p->r_min >= 0.f))
+        return SRT3D_EINVAL;
+    if (p->tau_z != p->tau_z) return SRT3D_EINVAL;   // NaN
+    return SRT3D_OK;
+}
+
+int check_state(const srt3d_state* st) {
+    if (!st) return SRT3D_EINVAL;
+    for (int b = 0; b < 2; ++b)
+        if (!st->t[b] || !st->alpha[b] || !st->active[b]) return SRT3D_EINVAL;
+    if (!st->hhat || !st->scal) return SRT3D_EINVAL;
+    if (st->cur != 0 && st->cur != 1) return SRT3D_EINVAL;
+    return SRT3D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void srt3d_params_default(srt3d_params* p, int32_t rows, int32_t cols, int32_t T, int32_t m, int32_t K_max) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->rows = rows;
+    p->cols = cols;
+    p->T = T;
+    p->m = m;
+    p->K_max = K_max;
+    p->iters = 50;
+    p->R = 2;
+    p->Rb = 1;
+    p->init_stride = 0;
+    p->eta_t = 1.f;
+    p->eta_a = 1.f;
+    p->lambda_z = 1.f;
+    p->tau_z = 0.f;
+    p->r_min = 1.f;
+}
+
+int srt3d_sketch(const int32_t* d_stamps, int64_t N, const int64_t* d_offsets, int32_t P, int32_t T, int32_t m,
+                 const float* d_table, float* d_z, int32_t* d_n, double* d_acc, int64_t* d_nacc, int32_t* d_err,
+                 void* stream) {
+    if (P < 1 || N < 0 || !sketch_dims_ok(T, m)) return SRT3D_EINVAL;
+    if ((!d_stamps && N > 0) || !d_offsets || !d_table || !d_z || !d_n) return SRT3D_EINVAL;
+    if ((d_acc == nullptr) != (d_nacc == nullptr)) return SRT3D_EINVAL;
+    if (!aligned(d_table, 8) || !aligned(d_z, 8)) return SRT3D_EINVAL;
+    return dev_status(launch_sketch_photons(d_stamps, N, d_offsets, P, T, m, reinterpret_cast<const float2*>(d_table),
+                                            d_z, d_n, d_acc, d_nacc, d_err, as_stream(stream)));
+}
+
+size_t srt3d_hist_workspace_bytes(int32_t T, int32_t m, int32_t precision) {
+    if (!sketch_dims_ok(T, m) || m > 32 || precision < 0 || precision > 2) return 0;
+    return hist_ws_bytes(T, m, precision);
+}
+
+int srt3d_hist_prepare(int32_t T, int32_t m, int32_t precision, void* d_ws, size_t ws_bytes, void* stream) {
+    if (!sketch_dims_ok(T, m) || m > 32 || T % 32 != 0) return SRT3D_EINVAL;
+    if (precision < SRT3D_PREC_FP32 || precision > SRT3D_PREC_BF16X3) return SRT3D_EINVAL;
+    if (!d_ws || !aligned(d_ws, 16)) return SRT3D_EINVAL;
+    if (ws_bytes < hist_ws_bytes(T, m, precision)) return SRT3D_ENOMEM;
+    return dev_status(launch_hist_prepare(T, m, precision, d_ws, as_stream(stream)));
+}
+
+int srt3d_sketch_from_hist(const uint16_t* d_hist, int32_t P, int32_t T, int32_t m, int32_t precision,
+                           const void* d_ws, size_t ws_bytes, float* d_z, int32_t* d_n, void* stream) {
+    if (P < 1 || !sketch_dims_ok(T, m) || m > 32 || T % 32 != 0) return SRT3D_EINVAL;
+    if (precision < SRT3D_PREC_FP32 || precision > SRT3D_PREC_BF16X3) return SRT3D_EINVAL;
+    if (!d_hist || !d_z || !d_n || !d_ws) return SRT3D_EINVAL;
+    if (!aligned(d_hist, 16) || !aligned(d_ws, 16)) return SRT3D_EINVAL;
+    if (ws_bytes < hist_ws_bytes(T, m, precision)) return SRT3D_ENOMEM;
+    return dev_status(launch_sketch_hist(d_hist, P, T, m, precision, d_ws, d_z, d_n, as_stream(stream)));
+}
+
+size_t srt3d_init_workspace_bytes(const srt3d_params* p) {
+    if (check_params(p) != SRT3D_OK) return 0;
+    return init_ws_bytes(*p);
+}
+
+int srt3d_init(const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len, int32_t irf_origin,
+               const srt3d_params* p, srt3d_state* st, void* d_ws, size_t ws_bytes, void* stream) {
+    int rc = check_params(p);
+    if (rc != SRT3D_OK) return rc;
+    if ((rc = check_state(st)) != SRT3D_OK) return rc;
+    if (!d_z || !d_n || !d_irf || !d_ws || irf_len < 1 || irf_origin < 0 || irf_origin >= irf_len)
+        return SRT3D_EINVAL;
+    if (!aligned(d_ws, 16) || !aligned(d_z, 8) || !aligned(st->hhat, 8)) return SRT3D_EINVAL;
+    if (ws_bytes < init_ws_bytes(*p)) return SRT3D_ENOMEM;
+    st->cur = 0;
+    return dev_status(launch_init(d_z, d_n, d_irf, irf_len, irf_origin, *p, *st, d_ws, as_stream(stream)));
+}
+
+int srt3d_step(srt3d_state* st, const float* d_z, const int32_t* d_n, const srt3d_params* p, int32_t stage,
+               void* stream) {
+    int rc = check_params(p);
+    if (rc != SRT3D_OK) return rc;
+    if ((rc = check_state(st)) != SRT3D_OK) return rc;
+    if (!d_n || (stage == SRT3D_STAGE_DATA && !d_z)) return SRT3D_EINVAL;
+    hipStream_t s = as_stream(stream);
+    const int c = st->cur;
+    hipError_t e;
+    switch (stage) {
+        case SRT3D_STAGE_DATA: e = launch_data_step(*p, d_z, d_n, *st, c, s); break;
+        case SRT3D_STAGE_DEPTH: e = launch_depth_denoise(*p, *st, c, 1 - c, s); break;
+        case SRT3D_STAGE_INTENSITY: e = launch_intensity_denoise(*p, d_n, *st, c, 1 - c, s); break;
+        default: return SRT3D_EINVAL;
+    }
+    if (e != hipSuccess) return SRT3D_EDEVICE;
+    if (stage != SRT3D_STAGE_DATA) st->cur = 1 - c;
+    return SRT3D_OK;
+}
+
+int srt3d_iterate(srt3d_state* st, const float* d_z, const int32_t* d_n, const srt3d_params* p, int32_t iters,
+                  void* stream) {
+    int rc = check_params(p);
+    if (rc != SRT3D_OK) return rc;
+    if ((rc = check_state(st)) != SRT3D_OK) return rc;
+    if (!d_z || !d_n || iters < 0) return SRT3D_EINVAL;
+    for (int it = 0; it < iters; ++it)
+        for (int stage = 0; stage < 3; ++stage)
+            if ((rc = srt3d_step(st, d_z, d_n, p, stage, stream)) != SRT3D_OK) return rc;
+    return SRT3D_OK;
+}
+
+int srt3d_finalize(const srt3d_state* st, const int32_t* d_n, const srt3d_params* p, float* d_depth,
+                   float* d_intensity, uint8_t* d_active, float* d_bg, void* stream) {
+    int rc = check_params(p);
+    if (rc != SRT3D_OK) return rc;
+    if ((rc = check_state(st)) != SRT3D_OK) return rc;
+    if (!d_n) return SRT3D_EINVAL;
+    return dev_status(launch_finalize(*p, d_n, *st, d_depth, d_intensity, d_active, d_bg, as_stream(stream)));
+}
+
+int srt3d_reconstruct(const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len,
+                      int32_t irf_origin, const srt3d_params* p, srt3d_state* st, float* d_depth,
+                      float* d_intensity, uint8_t* d_active, float* d_bg, void* d_ws, size_t ws_bytes,
+                      void* stream) {
+    int rc = srt3d_init(d_z, d_n, d_irf, irf_len, irf_origin, p, st, d_ws, ws_bytes, stream);
+    if (rc != SRT3D_OK) return rc;
+    if ((rc = srt3d_iterate(st, d_z, d_n, p, p->iters, stream)) != SRT3D_OK) return rc;
+    return srt3d_finalize(st, d_n, p, d_depth, d_intensity, d_active, d_bg, stream);
+}
+
+int srt3d_phase_indices(const int32_t* d_x, int64_t N, int32_t T, int32_t m, int32_t* d_k, void* stream) {
+    if (N < 0 || !sketch_dims_ok(T, m) || (N > 0 && (!d_x || !d_k))) return SRT3D_EINVAL;
+    return dev_status(launch_phase_indices(d_x, N, T, m, d_k, as_stream(stream)));
+}
+
+int srt3d_phase_table(int32_t T, float* d_table, void* stream) {
+    if (T < 2 || (int64_t)T * 8 > 65536 || !d_table || !aligned(d_table, 8)) return SRT3D_EINVAL;
+    return dev_status(launch_phase_table(T, reinterpret_cast<float2*>(d_table), as_stream(stream)));
+}
+
+const char* srt3d_strerror(int status) {
+    switch (status) {
+        case SRT3D_OK: return "ok";
+        case SRT3D_EINVAL: return "invalid argument";
+        case SRT3D_ENOMEM: return "workspace too small";
+        case SRT3D_EDEVICE: return "HIP device error";
+        default: return "unknown status";
+    }
+}
+
+int srt3d_version(void) { return SRT3D_VERSION; }
+
+}  // extern "C"

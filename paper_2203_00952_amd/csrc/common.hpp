@@ -1,0 +1,58 @@
+// Shared device helpers and the internal launch interface of libsrt3d.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "srt3d.h"
+
+namespace srt3d {
+
+constexpr int kWave = 64;
+
+// Bytes of the workspace given to the phase table (T float2 entries), 256-byte aligned.
+inline size_t table_bytes(int T) { return ((size_t)T * 8 + 255) & ~(size_t)255; }
+
+// Exact phase advance: k <- (k + x) mod T for k, x in [0, T).  The power-of-two form keeps
+// a byte offset (k * 8) so the result addresses the float2 table directly.
+template <bool POW2>
+__device__ __forceinline__ uint32_t phase_advance(uint32_t k8, uint32_t x8, uint32_t T8) {
+    if constexpr (POW2) {
+        return (k8 + x8) & (T8 - 1u);
+    } else {
+        uint32_t a = k8 + x8;
+        return a >= T8 ? a - T8 : a;
+    }
+}
+
+// Mathematical modulus of a signed stamp into [0, T).
+__device__ __forceinline__ int32_t fold_stamp(int32_t x, int32_t T) {
+    int32_t r = x % T;
+    return r < 0 ? r + T : r;
+}
+
+__device__ __forceinline__ float shfl_xor_f(float v, int mask) { return __shfl_xor(v, mask, kWave); }
+
+// Launch wrappers (defined in the .hip files).  All return hipSuccess or the launch error.
+hipError_t launch_phase_table(int T, float2* table, hipStream_t s);
+hipError_t launch_phase_indices(const int32_t* x, int64_t N, int T, int m, int32_t* k, hipStream_t s);
+hipError_t launch_sketch_photons(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T,
+                                 int m, const float2* table, float* z, int32_t* n, double* acc,
+                                 int64_t* nacc, int32_t* err, hipStream_t s);
+hipError_t launch_hist_prepare(int T, int m, int precision, void* ws, hipStream_t s);
+hipError_t launch_sketch_hist(const uint16_t* hist, int P, int T, int m, int precision, const void* ws,
+                              float* z, int32_t* n, hipStream_t s);
+size_t hist_ws_bytes(int T, int m, int precision);
+
+hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int irf_len, int irf_origin,
+                       const srt3d_params& p, const srt3d_state& st, void* ws, hipStream_t s);
+hipError_t launch_data_step(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st,
+                            int cur, hipStream_t s);
+hipError_t launch_depth_denoise(const srt3d_params& p, const srt3d_state& st, int src, int dst, hipStream_t s);
+hipError_t launch_intensity_denoise(const srt3d_params& p, const int32_t* n, const srt3d_state& st, int src,
+                                    int dst, hipStream_t s);
+hipError_t launch_finalize(const srt3d_params& p, const int32_t* n, const srt3d_state& st, float* depth,
+                           float* intensity, uint8_t* active, float* bg, hipStream_t s);
+size_t init_ws_bytes(const srt3d_params& p);
+
+}  // namespace srt3d

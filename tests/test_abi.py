@@ -1,0 +1,122 @@
+"""The C ABI library: it loads, exports every declared entry point, and rejects invalid
+arguments on the host before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2203_00952_amd as srt
+from paper_2203_00952_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "srt3d.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(srt3d_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libsrt3d.so is not built (run __graft_entry__.build())")
+    return L._lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_version_and_strerror(lib):
+    assert lib.srt3d_version() == 1
+    assert lib.srt3d_strerror(0) == b"ok"
+    assert lib.srt3d_strerror(-1) == b"invalid argument"
+    assert lib.srt3d_strerror(-2) == b"workspace too small"
+
+
+def test_params_default(lib):
+    p = srt.Params.default(256, 256, 4096, 16)
+    assert (p.iters, p.R, p.Rb, p.init_stride) == (50, 2, 1, 0)
+    assert (p.eta_t, p.eta_a, p.lambda_z, p.tau_z, p.r_min) == (1.0, 1.0, 1.0, 0.0, 1.0)
+
+
+def test_workspace_queries(lib):
+    assert lib.srt3d_hist_workspace_bytes(1024, 16, 0) == 32 * 1024 * 4
+    assert lib.srt3d_hist_workspace_bytes(1024, 16, 1) == 2 * 32 * 1024 * 2
+    assert lib.srt3d_hist_workspace_bytes(1024, 16, 2) == 3 * 32 * 1024 * 2
+    assert lib.srt3d_hist_workspace_bytes(1024, 33, 0) == 0
+    assert lib.srt3d_hist_workspace_bytes(1024, 16, 3) == 0
+    assert lib.srt3d_hist_workspace_bytes(16384, 4, 0) == 0
+    p = L._Params()
+    lib.srt3d_params_default(ctypes.byref(p), 32, 32, 1024, 4, 1)
+    assert lib.srt3d_init_workspace_bytes(ctypes.byref(p)) == 1024 * 8
+    p.K_max = 4
+    assert lib.srt3d_init_workspace_bytes(ctypes.byref(p)) == 0
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    VP = ctypes.c_void_p
+    fake = VP(0x1000)   # never dereferenced: validation fails first
+    # P < 1, m > T/2, T too large, NULL table / outputs, acc without nacc, N < 0, misaligned z
+    assert lib.srt3d_sketch(fake, 10, fake, 0, 1024, 4, fake, fake, fake, None, None, None, None) == -1
+    assert lib.srt3d_sketch(fake, 10, fake, 4, 1024, 513, fake, fake, fake, None, None, None, None) == -1
+    assert lib.srt3d_sketch(fake, 10, fake, 4, 16384, 4, fake, fake, fake, None, None, None, None) == -1
+    assert lib.srt3d_sketch(fake, 10, fake, 4, 1024, 4, None, fake, fake, None, None, None, None) == -1
+    assert lib.srt3d_sketch(fake, 10, fake, 4, 1024, 4, fake, None, fake, None, None, None, None) == -1
+    assert lib.srt3d_sketch(fake, 10, fake, 4, 1024, 4, fake, fake, fake, fake, None, None, None) == -1
+    assert lib.srt3d_sketch(fake, -1, fake, 4, 1024, 4, fake, fake, fake, None, None, None, None) == -1
+    assert lib.srt3d_sketch(fake, 10, fake, 4, 1024, 4, fake, VP(0x1004), fake, None, None, None, None) == -1
+    assert lib.srt3d_phase_table(1, fake, None) == -1
+    # histogram: T not a multiple of 32, m > 32, bad precision, misaligned pointer, small workspace
+    assert lib.srt3d_hist_prepare(1000, 4, 0, fake, 1 << 20, None) == -1
+    assert lib.srt3d_hist_prepare(1024, 4, 0, fake, 16, None) == -2
+    assert lib.srt3d_sketch_from_hist(fake, 4, 1000, 4, 0, fake, 1 << 20, fake, fake, None) == -1
+    assert lib.srt3d_sketch_from_hist(fake, 4, 1024, 33, 0, fake, 1 << 20, fake, fake, None) == -1
+    assert lib.srt3d_sketch_from_hist(fake, 4, 1024, 4, 7, fake, 1 << 20, fake, fake, None) == -1
+    assert lib.srt3d_sketch_from_hist(VP(0x1002), 4, 1024, 4, 0, fake, 1 << 20, fake, fake, None) == -1
+    assert lib.srt3d_sketch_from_hist(fake, 4, 1024, 4, 0, fake, 16, fake, fake, None) == -2
+
+
+def test_invalid_reconstruction_arguments(lib):
+    fake = ctypes.c_void_p(0x1000)
+    p = L._Params()
+    lib.srt3d_params_default(ctypes.byref(p), 8, 8, 1024, 4, 1)
+    st = L._State()
+    for b in range(2):
+        st.t[b] = st.alpha[b] = st.active[b] = 0x1000
+    st.hhat = st.scal = 0x1000
+    args = (fake, fake, fake, 5, 2, ctypes.byref(p), ctypes.byref(st), fake, 1 << 20, None)
+    bad = [dict(K_max=4), dict(m=65), dict(R=4), dict(rows=0), dict(iters=-1), dict(eta_t=-1.0),
+           dict(init_stride=1024), dict(T=16384)]
+    for change in bad:
+        q = L._Params()
+        ctypes.pointer(q)[0] = p
+        for k, v in change.items():
+            setattr(q, k, v)
+        assert lib.srt3d_init(fake, fake, fake, 5, 2, ctypes.byref(q), ctypes.byref(st), fake, 1 << 20, None) == -1
+    assert lib.srt3d_init(fake, fake, fake, 5, 5, *args[5:]) == -1            # origin outside irf
+    assert lib.srt3d_init(fake, fake, fake, 0, 0, *args[5:]) == -1            # empty irf
+    assert lib.srt3d_init(*args[:7], fake, 16, None) == -2                    # workspace too small
+    st2 = L._State()
+    ctypes.pointer(st2)[0] = st
+    st2.cur = 2
+    assert lib.srt3d_step(ctypes.byref(st2), fake, fake, ctypes.byref(p), 0, None) == -1
+    assert lib.srt3d_step(ctypes.byref(st), fake, fake, ctypes.byref(p), 3, None) == -1
+    st2.cur = 0
+    st2.scal = None
+    assert lib.srt3d_iterate(ctypes.byref(st2), fake, fake, ctypes.byref(p), 1, None) == -1
+    assert lib.srt3d_phase_table(16384, fake, None) == -1
+    assert lib.srt3d_phase_indices(fake, 10, 1024, 0, fake, None) == -1
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    with pytest.raises(TypeError):
+        srt.sketch(torch.zeros(4, dtype=torch.int32), torch.zeros(3, dtype=torch.int64), 64, 4)

@@ -1,0 +1,235 @@
+"""GPU parity of the SRT3D reconstruction (eq. 8 with W = I plus denoisers) against the
+FP64 oracle, through the C ABI: frame constants, each stage from a shared state, whole
+iterations from a shared initialisation, and end to end."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2203_00952_amd as srt
+import synth
+from oracle import model as OM
+from oracle import sketch as OS
+from oracle import srt3d as O
+from tests.gpu_common import circ_abs, device, to_complex
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(**kw):
+    print("case", " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+class Frame:
+    """A synthetic frame sketched on the GPU, with the oracle's view of the same sketch."""
+
+    def __init__(self, spec, m, K, dev, **pk):
+        self.spec, self.m, self.K = spec, m, K
+        f = synth.make_frame(spec, device=dev)
+        self.f = f
+        self.z, self.n = srt.sketch(f.stamps, f.offsets, spec.T, m)
+        torch.cuda.synchronize()
+        self.zc = to_complex(self.z)                # the GPU's FP32 sketch, exactly, in FP64
+        self.nn = self.n.cpu().numpy().astype(np.int64)
+        self.irf = torch.from_numpy(f.irf).to(dev)
+        self.params = srt.Params.default(spec.rows, spec.cols, spec.T, m, K, **pk)
+        self.op = O.Params(spec.T, m, K, iters=self.params.iters, R=self.params.R, Rb=self.params.Rb,
+                           r_min=self.params.r_min, tau_z=self.params.tau_z)
+        self.hhat = OM.irf_spectrum(f.irf, f.irf_origin, spec.T, m)
+        self.tau_z = O.default_tau_z(f.irf, f.irf_origin, self.op)
+        self.gam = O.step_sizes(self.nn, self.hhat, self.op)
+        self.rec = srt.Reconstructor(self.params, dev)
+
+    def gpu_init(self):
+        self.rec.init(self.z, self.n, self.irf, self.f.irf_origin)
+
+    def upload(self, st: O.State):
+        self.rec.set_state(torch.from_numpy(st.t), torch.from_numpy(st.alpha), torch.from_numpy(st.active))
+
+    def download(self) -> O.State:
+        torch.cuda.synchronize()
+        t, a, act = (x.cpu().numpy() for x in self.rec.state())
+        return O.State(t.astype(np.float64), a.astype(np.float64), act.astype(bool))
+
+
+def tiny(dev, **pk):
+    w = synth.preset("tiny")
+    return Frame(w.frame, w.m, w.K_max, dev, **pk)
+
+
+def layered(dev, rows=48, cols=40, **pk):
+    spec = synth.FrameSpec(rows, cols, 8192, 8.0, 4000.0, 0.5, 3, seed=5)
+    return Frame(spec, 32, 3, dev, r_min=100.0, **pk)
+
+
+def pixel_pass(d_g, a_g, d_r, a_r, T, tol=1.0):
+    """Pixel passes iff the active sets agree and active depths agree within `tol` bins."""
+    a_g = a_g.astype(bool)
+    a_r = a_r.astype(bool)
+    same = (a_g == a_r).all(1)
+    close = ((circ_abs(d_g - d_r, T) <= tol) | ~a_r).all(1)
+    return same & close
+
+
+# ----------------------------------------------------------------------------- constants and init
+@pytest.mark.parametrize("make", [tiny, layered])
+def test_frame_constants(make):
+    dev = device()
+    fr = make(dev)
+    _case(test="constants", P=fr.spec.P, m=fr.m)
+    fr.gpu_init()
+    torch.cuda.synchronize()
+    hh = fr.rec.hhat.cpu().numpy()
+    np.testing.assert_allclose(hh[:, 0] + 1j * hh[:, 1], fr.hhat, atol=2e-7)
+    sc = fr.rec.scal.cpu().numpy()
+    assert sc[0] == fr.nn.max()
+    np.testing.assert_allclose(sc[1:3], fr.gam, rtol=1e-6)
+    np.testing.assert_allclose(sc[3], fr.tau_z, rtol=1e-6)
+
+
+@pytest.mark.parametrize("make", [tiny, layered])
+def test_init_matches_oracle(make):
+    dev = device()
+    fr = make(dev)
+    _case(test="init", P=fr.spec.P, K=fr.K)
+    fr.gpu_init()
+    g = fr.download()
+    r = O.init_points(fr.zc, fr.nn, fr.hhat, fr.op)
+    same_t = (g.t == r.t).all(1)
+    print("init: pixels with identical grid picks", same_t.mean())
+    assert same_t.mean() >= 0.999
+    np.testing.assert_array_equal(g.active[same_t], r.active[same_t])
+    np.testing.assert_allclose(g.alpha[same_t], r.alpha[same_t], atol=2e-5)
+
+
+# ----------------------------------------------------------------------------- one stage at a time
+def _prepared_state(fr, data_steps=2):
+    st = O.init_points(fr.zc, fr.nn, fr.hhat, fr.op)
+    for _ in range(data_steps):
+        st = O.data_step(st, fr.zc, fr.nn, fr.hhat, fr.op, *fr.gam)
+        st = O.depth_denoise(st, fr.spec.rows, fr.spec.cols, fr.op, fr.tau_z)
+    return st
+
+
+@pytest.mark.parametrize("make", [tiny, layered])
+def test_each_stage_from_shared_state(make):
+    dev = device()
+    fr = make(dev)
+    rows, cols = fr.spec.rows, fr.spec.cols
+    fr.gpu_init()
+    st = _prepared_state(fr)
+    ref = {
+        "data": O.data_step(st, fr.zc, fr.nn, fr.hhat, fr.op, *fr.gam),
+        "depth": O.depth_denoise(st, rows, cols, fr.op, fr.tau_z),
+        "intensity": O.intensity_denoise(st, fr.nn, rows, cols, fr.op, fr.tau_z),
+    }
+    for stage, r in ref.items():
+        _case(test="stage", stage=stage, P=fr.spec.P, K=fr.K)
+        fr.upload(st)
+        fr.rec.step(stage, fr.z, fr.n)
+        g = fr.download()
+        act_ok = (g.active == r.active).all(1)
+        t_ok = ((circ_abs(g.t - r.t, fr.spec.T) <= 2e-3) | ~r.active).all(1)
+        a_ok = ((np.abs(g.alpha - r.alpha) <= 1e-4) | ~r.active).all(1)
+        frac = (act_ok & t_ok & a_ok).mean()
+        print(stage, "fraction of pixels within 2e-3 bins / 1e-4 alpha:", frac)
+        assert frac >= 0.999
+
+
+@pytest.mark.parametrize("make", [tiny, layered])
+def test_finalize_from_shared_state(make):
+    dev = device()
+    fr = make(dev)
+    fr.gpu_init()
+    st = _prepared_state(fr)
+    fr.upload(st)
+    _case(test="finalize", P=fr.spec.P)
+    out = fr.rec.finalize(fr.n)
+    torch.cuda.synchronize()
+    d, r, a = O.output(st, fr.nn)
+    np.testing.assert_array_equal(out["active"].cpu().numpy().astype(bool), a)
+    np.testing.assert_allclose(out["depth"].cpu().numpy(), d, atol=1e-3)
+    np.testing.assert_allclose(out["intensity"].cpu().numpy(), r, rtol=1e-5, atol=1e-3)
+    bg = O.background(st, fr.nn, fr.spec.rows, fr.spec.cols, fr.op)
+    np.testing.assert_allclose(out["bg"].cpu().numpy(), bg, rtol=1e-5, atol=1e-6)
+
+
+# ----------------------------------------------------------------------------- whole iterations
+@pytest.mark.parametrize("make", [tiny, layered])
+def test_iterations_from_shared_init(make):
+    dev = device()
+    fr = make(dev)
+    fr.gpu_init()
+    st0 = O.init_points(fr.zc, fr.nn, fr.hhat, fr.op)
+    fr.upload(st0)
+    iters = 50 if fr.K == 1 else 20
+    _case(test="iterations", P=fr.spec.P, iters=iters)
+    fr.rec.iterate(fr.z, fr.n, iters)
+    out = fr.rec.finalize(fr.n)
+    torch.cuda.synchronize()
+    r = O.iterate(st0, fr.zc, fr.nn, fr.hhat, fr.spec.rows, fr.spec.cols, fr.op, fr.tau_z, iters)
+    d, _, a = O.output(r, fr.nn)
+    ok = pixel_pass(out["depth"].cpu().numpy(), out["active"].cpu().numpy(), d, a, fr.spec.T)
+    print("pixels within 1 bin:", ok.mean(), "failing:", int((~ok).sum()))
+    assert ok.mean() >= 0.999
+
+
+def test_end_to_end_tiny_with_independent_oracle_sketch():
+    """Oracle sketches the stamps itself in FP64 and reconstructs; GPU does everything."""
+    dev = device()
+    fr = tiny(dev)
+    _case(test="e2e_tiny")
+    out = fr.rec.reconstruct(fr.z, fr.n, fr.irf, fr.f.irf_origin)
+    torch.cuda.synchronize()
+    z_ref, n_ref = OS.sketch(fr.f.stamps.cpu().numpy(), fr.f.offsets.cpu().numpy(), fr.spec.T, fr.m)
+    r = O.reconstruct(z_ref, n_ref, fr.f.irf, fr.f.irf_origin, fr.spec.rows, fr.spec.cols, fr.op)
+    ok = pixel_pass(out["depth"].cpu().numpy(), out["active"].cpu().numpy(), r["depth"], r["active"], fr.spec.T)
+    print("tiny end to end: pixels within 1 bin", ok.mean())
+    assert ok.mean() >= 0.999
+    np.testing.assert_allclose(out["bg"].cpu().numpy(), r["bg"], rtol=1e-3, atol=1e-6)
+
+
+def test_end_to_end_throughput_frame():
+    """256x256, T=4096, m=16, 50 iterations: GPU reconstruct vs oracle reconstruct of the same sketch."""
+    dev = device()
+    w = synth.preset("throughput")
+    fr = Frame(w.frame, w.m, w.K_max, dev)
+    _case(test="e2e_throughput")
+    out = fr.rec.reconstruct(fr.z, fr.n, fr.irf, fr.f.irf_origin)
+    torch.cuda.synchronize()
+    r = O.reconstruct(fr.zc, fr.nn, fr.f.irf, fr.f.irf_origin, fr.spec.rows, fr.spec.cols, fr.op)
+    ok = pixel_pass(out["depth"].cpu().numpy(), out["active"].cpu().numpy(), r["depth"], r["active"], fr.spec.T)
+    print("throughput end to end: pixels within 1 bin", ok.mean(), "failing", int((~ok).sum()))
+    assert ok.mean() >= 0.999
+    truth = fr.f.scene.depth[:, 0]
+    err = circ_abs(out["depth"].cpu().numpy()[:, 0] - truth, fr.spec.T)
+    print("median |depth - truth| (bins):", float(np.median(err)))
+
+
+def test_end_to_end_layered():
+    dev = device()
+    fr = layered(dev)
+    _case(test="e2e_layered")
+    out = fr.rec.reconstruct(fr.z, fr.n, fr.irf, fr.f.irf_origin)
+    torch.cuda.synchronize()
+    r = O.reconstruct(fr.zc, fr.nn, fr.f.irf, fr.f.irf_origin, fr.spec.rows, fr.spec.cols, fr.op)
+    ok = pixel_pass(out["depth"].cpu().numpy(), out["active"].cpu().numpy(), r["depth"], r["active"], fr.spec.T)
+    print("layered end to end: pixels within 1 bin", ok.mean(), "failing", int((~ok).sum()))
+    assert ok.mean() >= 0.995
+
+
+def test_deterministic_and_resumable():
+    dev = device()
+    fr = tiny(dev)
+    _case(test="determinism")
+    a = fr.rec.reconstruct(fr.z, fr.n, fr.irf, fr.f.irf_origin)
+    b = fr.rec.reconstruct(fr.z, fr.n, fr.irf, fr.f.irf_origin)
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+    fr.gpu_init()
+    fr.rec.iterate(fr.z, fr.n, 20)
+    fr.rec.iterate(fr.z, fr.n, 30)
+    c = fr.rec.finalize(fr.n)
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k], c[k]), k
