@@ -1,26 +1,33 @@
 // Sketched RT3D iteration, Section 3: eq. (8) with W = I, alternated with point-cloud and
 // intensity denoising (RT3D's plug-and-play scheme).
 //
-//   frame_constants  hhat_l = sum_i h_i exp(i w_l (i - o)) / sum h (eq. 4), n_max, step sizes,
-//                    depth gate (one workgroup, FP64)
-//   init             greedy sketched matched filter on the grid tau = 0, s, 2s, ...: one wave
-//                    per pixel, lanes over grid points, exact phases (l tau) mod T from an LDS
-//                    table
-//   data_step        per pixel: residual e = Phi - z, depth step, residual at the new depths,
-//                    intensity step, projection onto {alpha >= 0, sum alpha <= 1} (eq. 1);
-//                    streams over harmonics so no per-harmonic arrays are kept
-//   depth_denoise    per point: weighted least-squares height-field fit over a gated
-//                    (2R+1)^2 window (4x4 Cholesky, plane and mean fallbacks)
+//   frame_constants   hhat_l = sum_i h_i exp(i w_l (i - o)) / sum h (eq. 4) in FP64, the sums
+//                     sum |hhat|^2 and sum w^2 |hhat|^2, the impulse-response spread and the
+//                     depth gate; one workgroup, one wave per harmonic subset
+//   init              greedy sketched matched filter on the grid tau = 0, s, 2s, ...: one wave per
+//                     pixel, lanes over grid points, harmonics by a phasor recurrence re-anchored
+//                     every 16 harmonics at the exact integer phase (l tau) mod T; also the
+//                     per-workgroup maximum photon count
+//   step_sizes        frame maximum photon count and the two step sizes
+//   data_step         per pixel: residual e = Phi - z, depth step, residual at the new depths,
+//                     intensity step, projection onto {alpha >= 0, sum alpha <= 1} (eq. 1);
+//                     the workgroup's sketches are staged in LDS by coalesced loads
+//   depth_denoise     per point: weighted least-squares height-field fit over a gated
+//                     (2R+1)^2 window (4x4 Cholesky, plane and mean fallbacks); 16x16 pixel
+//                     tiles with an R-pixel halo in LDS
 //   intensity_denoise per point: gated weighted mean of n * alpha, removal below r_min
-//   finalize         background n * max(0, 1 - sum alpha) / T with a box filter, output
-//                    points sorted by depth
+//   finalize          background n * max(0, 1 - sum alpha) / T with a box filter, output
+//                     points sorted by depth
 // Every kernel writes only its own pixels; denoisers read one buffer and write the other.
 #include "common.hpp"
 
 namespace srt3d {
 
 constexpr int kMaxW = (2 * SRT3D_MAX_R + 1) * (2 * SRT3D_MAX_R + 1);
-constexpr float kCholEps = 1e-5f;   // pivot <= kCholEps * trace counts as singular
+constexpr float kCholEps = 1e-5f;    // pivot <= kCholEps * trace counts as singular
+constexpr int kTile = 16;            // denoiser tile edge (pixels)
+constexpr int kInitBlocksMax = 4096; // init workgroups (bounds the partial-max buffer)
+constexpr int kDataThreads = 128;    // pixels per data-step workgroup (64 when m > 60)
 
 struct IterArgs {
     int rows, cols, P, T, m, K, R, Rb;
@@ -40,6 +47,13 @@ __device__ __forceinline__ float wrap_t(float t, float Tf) {
 __device__ __forceinline__ float circ_diff(float d, float Tf) {
     float r = wrap_t(d, Tf);
     return r > 0.5f * Tf ? r - Tf : r;
+}
+
+// exp(i 2 pi k / T) for an integer phase k in [0, 2T).
+__device__ __forceinline__ float2 phasor_int(int k, int T) {
+    float s, c;
+    sincospif((2.0f * (float)k) / (float)T, &s, &c);
+    return make_float2(c, s);
 }
 
 // exp(i w_l t) with the phase (l t) mod T reduced through the integer part of t.
@@ -94,152 +108,140 @@ __device__ __forceinline__ void project_capped_simplex(float* a, const bool* act
     for (int k = 0; k < K; ++k) a[k] = act[k] ? fmaxf(a[k] - theta, 0.f) : 0.f;
 }
 
+__device__ __forceinline__ double wave_sum_d(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 // ----------------------------------------------------------------------------- frame constants
-// scal: [0] n_max, [1] gamma_t, [2] gamma_alpha, [3] tau_z, [4] sum |hhat|^2
-__global__ __launch_bounds__(256) void frame_constants_kernel(const int32_t* __restrict__ n, int P,
-                                                              const double* __restrict__ irf, int irf_len,
-                                                              int origin, int T, int m, int K, float eta_t,
-                                                              float eta_a, float tau_z_param,
+// scal: [0] n_max, [1] gamma_t, [2] gamma_alpha, [3] tau_z, [4] sum |hhat|^2, [5] sum w^2 |hhat|^2
+__global__ __launch_bounds__(256) void frame_constants_kernel(const double* __restrict__ irf, int irf_len,
+                                                              int origin, int T, int m, float tau_z_param,
                                                               float* __restrict__ hhat_out,
                                                               float* __restrict__ scal) {
-    __shared__ int s_max[256];
-    __shared__ double s_e2[256], s_et[256];
-    __shared__ double s_h[3][256];
-    const int tid = threadIdx.x;
-    int mx = 0;
-    for (int p = tid; p < P; p += blockDim.x) mx = max(mx, n[p]);
-    s_max[tid] = mx;
-    // impulse response moments: sum h, sum h*lag, sum h*lag^2
-    double h0 = 0, h1 = 0, h2 = 0;
-    for (int i = tid; i < irf_len; i += blockDim.x) {
-        const double lag = (double)(i - origin);
-        h0 += irf[i];
-        h1 += irf[i] * lag;
-        h2 += irf[i] * lag * lag;
-    }
-    s_h[0][tid] = h0;
-    s_h[1][tid] = h1;
-    s_h[2][tid] = h2;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o) {
-            s_max[tid] = max(s_max[tid], s_max[tid + o]);
-            s_h[0][tid] += s_h[0][tid + o];
-            s_h[1][tid] += s_h[1][tid + o];
-            s_h[2][tid] += s_h[2][tid + o];
+    __shared__ double s_e2[SRT3D_MAX_M_RECON], s_et[SRT3D_MAX_M_RECON];
+    __shared__ double s_mom[3];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // moments of the impulse response (wave 0): sum h, sum h lag, sum h lag^2
+    if (wv == 0) {
+        double h0 = 0, h1 = 0, h2 = 0;
+        for (int i = lane; i < irf_len; i += 64) {
+            const double lag = (double)(i - origin);
+            h0 += irf[i];
+            h1 += irf[i] * lag;
+            h2 += irf[i] * lag * lag;
         }
-        __syncthreads();
+        h0 = wave_sum_d(h0);
+        h1 = wave_sum_d(h1);
+        h2 = wave_sum_d(h2);
+        if (lane == 0) {
+            s_mom[0] = h0;
+            s_mom[1] = h1;
+            s_mom[2] = h2;
+        }
     }
-    const double H = s_h[0][0];
-    double e2 = 0, et = 0;
-    if (tid < m) {
-        const int l = tid + 1;
+    __syncthreads();
+    const double H = s_mom[0];
+    // hhat_l, harmonics distributed over the waves, lags over the lanes
+    for (int l = 1 + wv; l <= m; l += blockDim.x >> 6) {
         double re = 0, im = 0;
-        for (int i = 0; i < irf_len; ++i) {
-            int64_t k = ((int64_t)l * (i - origin)) % T;
+        for (int i = lane; i < irf_len; i += 64) {
+            int k = (int)(((int64_t)l * (i - origin)) % T);
             if (k < 0) k += T;
             double s, c;
             sincospi(2.0 * (double)k / (double)T, &s, &c);
             re += irf[i] * c;
             im += irf[i] * s;
         }
-        re /= H;
-        im /= H;
-        hhat_out[2 * tid] = (float)re;
-        hhat_out[2 * tid + 1] = (float)im;
-        const double w = 2.0 * M_PI * (double)l / (double)T;
-        e2 = re * re + im * im;
-        et = w * w * e2;
-    }
-    s_e2[tid] = e2;
-    s_et[tid] = et;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o) {
-            s_e2[tid] += s_e2[tid + o];
-            s_et[tid] += s_et[tid + o];
+        re = wave_sum_d(re) / H;
+        im = wave_sum_d(im) / H;
+        if (lane == 0) {
+            hhat_out[2 * (l - 1)] = (float)re;
+            hhat_out[2 * (l - 1) + 1] = (float)im;
+            const double w = 2.0 * M_PI * (double)l / (double)T;
+            s_e2[l - 1] = re * re + im * im;
+            s_et[l - 1] = w * w * (re * re + im * im);
         }
-        __syncthreads();
     }
-    if (tid == 0) {
-        const double nmax = (double)s_max[0];
-        const double mu = s_h[1][0] / H;
-        const double var = s_h[2][0] / H - mu * mu;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double e2 = 0, et = 0;
+        for (int l = 0; l < m; ++l) {
+            e2 += s_e2[l];
+            et += s_et[l];
+        }
+        const double mu = s_mom[1] / H;
+        const double var = s_mom[2] / H - mu * mu;
         const double sigma = sqrt(var > 0 ? var : 0.0);
-        scal[0] = (float)nmax;
-        scal[1] = nmax > 0 ? (float)(eta_t / (2.0 * nmax * s_et[0])) : 0.f;
-        scal[2] = nmax > 0 ? (float)(eta_a / (2.0 * nmax * K * s_e2[0])) : 0.f;
         scal[3] = tau_z_param > 0 ? tau_z_param : (float)(3.0 * sigma);
-        scal[4] = (float)s_e2[0];
-        for (int i = 5; i < SRT3D_NSCAL; ++i) scal[i] = 0.f;
+        scal[4] = (float)e2;
+        scal[5] = (float)et;
+        scal[6] = 0.f;
+        scal[7] = 0.f;
     }
 }
 
 // ----------------------------------------------------------------------------- init
-// One wave per pixel.  c(tau_g) = Re sum_l conj(hhat_l) w_l exp(-i w_l tau_g).
+// One wave per pixel.  c(tau_g) = Re sum_l conj(hhat_l) w_l exp(-i w_l tau_g) for the lane's grid
+// points; y_l = conj(hhat_l) w_l is held by lane l - 1 and broadcast with readlane.
 template <int K>
 __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, const int32_t* __restrict__ n,
-                                                   const float2* __restrict__ table, const float* __restrict__ hhat,
-                                                   const float* __restrict__ scal, int P, int T, int m, int stride,
-                                                   float r_min, float* __restrict__ t_out,
-                                                   float* __restrict__ a_out, uint8_t* __restrict__ act_out) {
-    extern __shared__ float2 s_mem[];
-    float2* s_table = s_mem;                       // T entries
-    float2* s_y = s_mem + T;                       // 4 waves x SRT3D_MAX_M_RECON
-    for (int i = threadIdx.x; i < T; i += blockDim.x) s_table[i] = table[i];
-    __syncthreads();
+                                                   const float* __restrict__ hhat, const float* __restrict__ scal,
+                                                   int P, int T, int m, int stride, float r_min,
+                                                   float* __restrict__ t_out, float* __restrict__ a_out,
+                                                   uint8_t* __restrict__ act_out, int* __restrict__ nmax_part) {
+    __shared__ int s_nmax[4];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    float2* y = s_y + wv * SRT3D_MAX_M_RECON;
     const int G = (T + stride - 1) / stride;
     const float e2 = scal[4];
-    const uint32_t T8 = (uint32_t)T << 3;
-    const bool pow2 = (T & (T - 1)) == 0;
     const int waves_total = gridDim.x * (blockDim.x >> 6);
+    int nmax = 0;
+    const float2 hl = lane < m ? reinterpret_cast<const float2*>(hhat)[lane] : make_float2(0.f, 0.f);
 
     for (int pix = blockIdx.x * (blockDim.x >> 6) + wv; pix < P; pix += waves_total) {
-        // working sketch w_l, one harmonic per lane (m <= 64)
-        float2 wl = make_float2(0.f, 0.f), hl = make_float2(0.f, 0.f);
-        if (lane < m) {
-            wl = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m)[lane];
-            hl = reinterpret_cast<const float2*>(hhat)[lane];
-        }
+        float2 wl = lane < m ? reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m)[lane] : make_float2(0.f, 0.f);
         const int np = n[pix];
+        nmax = max(nmax, np);
         int tau[K];
         float amp[K];
+#pragma unroll
         for (int k = 0; k < K; ++k) {
-            // y_l = conj(hhat_l) * w_l
-            if (lane < m) y[lane] = make_float2(hl.x * wl.x + hl.y * wl.y, hl.x * wl.y - hl.y * wl.x);
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            const float yx = hl.x * wl.x + hl.y * wl.y;    // conj(hhat) * w
+            const float yy = hl.x * wl.y - hl.y * wl.x;
             float best = -INFINITY;
             int bestg = 0x7fffffff;
-            for (int g = lane; g < G; g += 64) {
-                const int tg = g * stride;
-                bool excl = false;
+            // wave-uniform loops (every lane active): readlane reads lanes that hold y
+            for (int g0 = 0; g0 < G; g0 += 64) {
+                const int g = g0 + lane;
+                const int tg = (g < G ? g : 0) * stride;
+                bool skip = g >= G;
+#pragma unroll
                 for (int j = 0; j < k; ++j) {
                     int d = tg - tau[j];
                     d = d < 0 ? -d : d;
                     d = min(d, T - d);
-                    excl |= (int64_t)d * m < (int64_t)T;
+                    skip |= (int64_t)d * m < (int64_t)T;
                 }
-                if (excl) continue;
-                const uint32_t x8 = (uint32_t)tg << 3;
-                uint32_t k8 = 0;
+                float2 u1 = make_float2(1.f, 0.f), u = u1;
                 float c = 0.f;
                 for (int l = 0; l < m; ++l) {
-                    k8 = pow2 ? phase_advance<true>(k8, x8, T8) : phase_advance<false>(k8, x8, T8);
-                    const float2 cs = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(s_table) + k8);
-                    const float2 yl = y[l];
-                    c += yl.x * cs.x + yl.y * cs.y;   // Re(y e^{-i theta})
+                    if ((l & 15) == 0) {           // exact anchor: phase ((l+1) tau) mod T
+                        u = phasor_int((int)(((int64_t)(l + 1) * tg) % T), T);
+                        if (l == 0) u1 = u;
+                    } else {
+                        u = cmul(u, u1);
+                    }
+                    const float ax = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yx), l));
+                    const float ay = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yy), l));
+                    c += ax * u.x + ay * u.y;      // Re(y_l exp(-i w_l tau))
                 }
-                if (c > best) {               // g increases per lane, so ties keep the smaller g
+                if (!skip && c > best) {           // g increases per lane: ties keep the smaller g
                     best = c;
                     bestg = g;
                 }
             }
-            // wave argmax: larger c, then smaller g
-            for (int o = 32; o > 0; o >>= 1) {
+            for (int o = 32; o > 0; o >>= 1) {     // wave argmax: larger c, then smaller g
                 const float ob = __shfl_xor(best, o, 64);
                 const int og = __shfl_xor(bestg, o, 64);
                 if (ob > best || (ob == best && og < bestg)) {
@@ -251,15 +253,11 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
             const int tk = (bestg == 0x7fffffff) ? 0 : bestg * stride;
             tau[k] = tk;
             amp[k] = a;
-            // w_l -= a * hhat_l * exp(i w_l tau)
-            if (lane < m) {
-                const uint32_t kk = (uint32_t)(((int64_t)(lane + 1) * tk) % T);
-                const float2 cs = s_table[kk];
-                const float2 g = cmul(hl, cs);
+            if (lane < m) {                        // w_l -= a hhat_l exp(i w_l tau)
+                const float2 g = cmul(hl, phasor_int((int)(((int64_t)(lane + 1) * tk) % T), T));
                 wl.x -= a * g.x;
                 wl.y -= a * g.y;
             }
-            __builtin_amdgcn_wave_barrier();
         }
         if (lane == 0) {
             bool all[K];
@@ -275,18 +273,96 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
             }
         }
     }
+    if (lane == 0) s_nmax[wv] = nmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int v = s_nmax[0];
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) v = max(v, s_nmax[i]);
+        nmax_part[blockIdx.x] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void step_sizes_kernel(const int* __restrict__ nmax_part, int parts, int K,
+                                                         float eta_t, float eta_a, float* __restrict__ scal) {
+    __shared__ int s[256];
+    int v = 0;
+    for (int i = threadIdx.x; i < parts; i += blockDim.x) v = max(v, nmax_part[i]);
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double nmax = (double)s[0];
+        const double e2 = (double)scal[4], et = (double)scal[5];
+        scal[0] = (float)nmax;
+        scal[1] = nmax > 0 ? (float)((double)eta_t / (2.0 * nmax * et)) : 0.f;
+        scal[2] = nmax > 0 ? (float)((double)eta_a / (2.0 * nmax * K * e2)) : 0.f;
+    }
 }
 
 // ----------------------------------------------------------------------------- data step
 template <int K>
-__global__ __launch_bounds__(256) void data_step_kernel(IterArgs A, const float* __restrict__ z,
-                                                        const int32_t* __restrict__ n,
-                                                        const float* __restrict__ hhat,
-                                                        const float* __restrict__ scal, float* __restrict__ t,
-                                                        float* __restrict__ alpha,
-                                                        const uint8_t* __restrict__ active) {
-    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= A.P) return;
+__device__ __forceinline__ void residual_pass(const float2* __restrict__ zs, const float2* __restrict__ hp, int m, int T,
+                                              const float* tk, const float* ak, const bool* on, float* gsum,
+                                              bool depth) {
+    float2 u[K], u1[K];
+    const float w1 = 6.283185307179586f / (float)T;
+    for (int l = 1; l <= m; ++l) {
+        const float2 h = hp[l - 1];
+        const float2 zl = zs[l - 1];
+        float2 g[K];
+        float2 e = make_float2(-zl.x, -zl.y);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!on[k]) continue;
+            if (l == 1) {
+                u1[k] = phasor(1, tk[k], T);
+                u[k] = u1[k];
+            } else if ((l & 7) == 1) {
+                u[k] = phasor(l, tk[k], T);
+            } else {
+                u[k] = cmul(u[k], u1[k]);
+            }
+            g[k] = cmul(h, u[k]);
+            e.x += ak[k] * g[k].x;
+            e.y += ak[k] * g[k].y;
+        }
+        if (depth) {
+            const float wl = w1 * (float)l;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (on[k]) gsum[k] += wl * (e.x * g[k].y - e.y * g[k].x);
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (on[k]) gsum[k] += e.x * g[k].x + e.y * g[k].y;
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(kDataThreads) void data_step_kernel(IterArgs A, const float* __restrict__ z,
+                                                                 const int32_t* __restrict__ n,
+                                                                 const float* __restrict__ hhat,
+                                                                 const float* __restrict__ scal,
+                                                                 float* __restrict__ t, float* __restrict__ alpha,
+                                                                 const uint8_t* __restrict__ active) {
+    extern __shared__ float s_z[];                 // [blockDim.x][2m + 2]
+    const int m = A.m, rs = 2 * m + 2;
+    const int nt = blockDim.x;
+    const int64_t p0 = (int64_t)blockIdx.x * nt;
+    const int npx = (int)min((int64_t)nt, (int64_t)A.P - p0);
+    // coalesced staging of the workgroup's sketches
+    const float* zb = z + p0 * 2 * m;
+    for (int i = threadIdx.x; i < npx * 2 * m; i += nt) {
+        const int r = i / (2 * m), c = i - r * (2 * m);
+        s_z[r * rs + c] = zb[i];
+    }
+    __syncthreads();
+    const int pix = (int)p0 + threadIdx.x;
+    if (threadIdx.x >= npx) return;
     float tk[K], ak[K];
     bool on[K];
     bool any = false;
@@ -301,72 +377,20 @@ __global__ __launch_bounds__(256) void data_step_kernel(IterArgs A, const float*
     const float nn = (float)n[pix];
     const float gam_t = scal[1], gam_a = scal[2];
     const float Tf = (float)A.T;
-    const float w1 = 6.283185307179586f / Tf;
-    const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * A.m);
+    const float2* zs = reinterpret_cast<const float2*>(s_z + threadIdx.x * rs);
     const float2* hp = reinterpret_cast<const float2*>(hhat);
 
-    // pass 1: depth gradient at (t, alpha)
     float gt[K];
-    float2 u[K], u1[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) gt[k] = 0.f;
-    for (int l = 1; l <= A.m; ++l) {
-        const float2 h = hp[l - 1];
-        const float2 zl = zp[l - 1];
-        float2 g[K];
-        float2 e = make_float2(-zl.x, -zl.y);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (!on[k]) continue;
-            if (l == 1) {
-                u1[k] = phasor(1, tk[k], A.T);
-                u[k] = u1[k];
-            } else if ((l & 7) == 1) {
-                u[k] = phasor(l, tk[k], A.T);
-            } else {
-                u[k] = cmul(u[k], u1[k]);
-            }
-            g[k] = cmul(h, u[k]);
-            e.x += ak[k] * g[k].x;
-            e.y += ak[k] * g[k].y;
-        }
-        const float wl = w1 * (float)l;
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (on[k]) gt[k] += wl * (e.x * g[k].y - e.y * g[k].x);
-    }
+    residual_pass<K>(zs, hp, m, A.T, tk, ak, on, gt, true);
 #pragma unroll
     for (int k = 0; k < K; ++k)
         if (on[k]) tk[k] = wrap_t(tk[k] - gam_t * (-2.f * nn * ak[k] * gt[k]), Tf);
-
-    // pass 2: intensity gradient at (t_new, alpha)
     float ga[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) ga[k] = 0.f;
-    for (int l = 1; l <= A.m; ++l) {
-        const float2 h = hp[l - 1];
-        const float2 zl = zp[l - 1];
-        float2 g[K];
-        float2 e = make_float2(-zl.x, -zl.y);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (!on[k]) continue;
-            if (l == 1) {
-                u1[k] = phasor(1, tk[k], A.T);
-                u[k] = u1[k];
-            } else if ((l & 7) == 1) {
-                u[k] = phasor(l, tk[k], A.T);
-            } else {
-                u[k] = cmul(u[k], u1[k]);
-            }
-            g[k] = cmul(h, u[k]);
-            e.x += ak[k] * g[k].x;
-            e.y += ak[k] * g[k].y;
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (on[k]) ga[k] += e.x * g[k].x + e.y * g[k].y;
-    }
+    residual_pass<K>(zs, hp, m, A.T, tk, ak, on, ga, false);
 #pragma unroll
     for (int k = 0; k < K; ++k)
         if (on[k]) ak[k] = ak[k] - gam_a * (2.f * nn * ga[k]);
@@ -379,8 +403,7 @@ __global__ __launch_bounds__(256) void data_step_kernel(IterArgs A, const float*
 }
 
 // ----------------------------------------------------------------------------- denoisers
-// Solve the d x d system (d = 4 or 3) packed as Ms (upper triangle row-major) by Cholesky with
-// the pivot rule; returns false if singular.  Only x[0] is needed.
+// Solve the leading D x D block of M x = b by Cholesky with the pivot rule; only x[0] is needed.
 template <int D>
 __device__ __forceinline__ bool chol_x0(const float (&M)[4][4], const float (&b)[4], float& x0) {
     float L[D][D];
@@ -421,48 +444,82 @@ __device__ __forceinline__ bool chol_x0(const float (&M)[4][4], const float (&b)
     return true;
 }
 
-template <int K>
-__global__ __launch_bounds__(256) void depth_denoise_kernel(IterArgs A, const float* __restrict__ scal,
-                                                            const float* __restrict__ t_in,
-                                                            const float* __restrict__ a_in,
-                                                            const uint8_t* __restrict__ act_in,
-                                                            float* __restrict__ t_out, float* __restrict__ a_out,
-                                                            uint8_t* __restrict__ act_out) {
-    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= A.P) return;
-    const int i = pix / A.cols, j = pix - (pix / A.cols) * A.cols;
+// Tile of (kTile + 2R)^2 pixels x K points in LDS.  Points outside the frame are inactive.
+template <int K, int R>
+struct Tile {
+    static constexpr int E = kTile + 2 * R;
+    float t[E * E * K];
+    float r[E * E * K];       // n * alpha (intensity denoiser only)
+    uint8_t act[E * E * K];
+};
+
+template <int K, int R, bool WITH_R>
+__device__ __forceinline__ void load_tile(Tile<K, R>& s, const IterArgs& A, const float* __restrict__ t_in,
+                                          const float* __restrict__ a_in, const uint8_t* __restrict__ act_in,
+                                          const int32_t* __restrict__ n, int i0, int j0) {
+    constexpr int E = Tile<K, R>::E;
+    for (int idx = threadIdx.x; idx < E * E * K; idx += kTile * kTile) {
+        const int k = idx % K, cell = idx / K;
+        const int gi = i0 - R + cell / E, gj = j0 - R + cell % E;
+        float tv = 0.f, rv = 0.f;
+        uint8_t av = 0;
+        if (gi >= 0 && gi < A.rows && gj >= 0 && gj < A.cols) {
+            const int64_t q = ((int64_t)gi * A.cols + gj) * K + k;
+            tv = t_in[q];
+            av = act_in[q];
+            if constexpr (WITH_R) rv = (float)n[(int64_t)gi * A.cols + gj] * a_in[q];
+        }
+        s.t[idx] = tv;
+        s.act[idx] = av;
+        if constexpr (WITH_R) s.r[idx] = rv;
+    }
+}
+
+template <int K, int R>
+__global__ __launch_bounds__(kTile * kTile) void depth_denoise_kernel(
+    IterArgs A, const float* __restrict__ scal, const float* __restrict__ t_in, const float* __restrict__ a_in,
+    const uint8_t* __restrict__ act_in, float* __restrict__ t_out, float* __restrict__ a_out,
+    uint8_t* __restrict__ act_out) {
+    constexpr int E = Tile<K, R>::E, W = 2 * R + 1;
+    __shared__ Tile<K, R> s;
+    const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
+    load_tile<K, R, false>(s, A, t_in, a_in, act_in, nullptr, i0, j0);
+    __syncthreads();
+    const int ti = threadIdx.x / kTile, tj = threadIdx.x % kTile;
+    const int i = i0 + ti, j = j0 + tj;
+    if (i >= A.rows || j >= A.cols) return;
     const float Tf = (float)A.T;
     const float tau_z = scal[3];
-    const int R = A.R, W = 2 * R + 1;
+    const int pix = i * A.cols + j;
+#pragma unroll
     for (int k = 0; k < K; ++k) {
         const int64_t q = (int64_t)pix * K + k;
-        const float tq = t_in[q];
-        const bool on = act_in[q] != 0;
+        const int c = ((ti + R) * E + (tj + R)) * K + k;
+        const float tq = s.t[c];
         a_out[q] = a_in[q];
-        act_out[q] = act_in[q];
-        if (!on) {
+        act_out[q] = s.act[c];
+        if (!s.act[c]) {
             t_out[q] = tq;
             continue;
         }
         float M[4][4] = {}, b[4] = {};
+#pragma unroll
         for (int di = -R; di <= R; ++di) {
-            const int ii = i + di;
-            if (ii < 0 || ii >= A.rows) continue;
+#pragma unroll
             for (int dj = -R; dj <= R; ++dj) {
-                const int jj = j + dj;
-                if (jj < 0 || jj >= A.cols) continue;
                 const float w = A.wgt[(di + R) * W + (dj + R)];
-                const int64_t nb = ((int64_t)ii * A.cols + jj) * K;
+                const float phi[4] = {1.f, (float)di, (float)dj, (float)(di * di + dj * dj)};
+#pragma unroll
                 for (int kk = 0; kk < K; ++kk) {
-                    if (!act_in[nb + kk]) continue;
-                    const float d = circ_diff(t_in[nb + kk] - tq, Tf);
+                    const int cn = ((ti + R + di) * E + (tj + R + dj)) * K + kk;
+                    if (!s.act[cn]) continue;
+                    const float d = circ_diff(s.t[cn] - tq, Tf);
                     if (!(fabsf(d) <= tau_z)) continue;
-                    const float phi[4] = {1.f, (float)di, (float)dj, (float)(di * di + dj * dj)};
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         b[r] += w * phi[r] * d;
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) M[r][c] += w * phi[r] * phi[c];
+                        for (int cc = 0; cc < 4; ++cc) M[r][cc] += w * phi[r] * phi[cc];
                     }
                 }
             }
@@ -475,48 +532,47 @@ __global__ __launch_bounds__(256) void depth_denoise_kernel(IterArgs A, const fl
     }
 }
 
-template <int K>
-__global__ __launch_bounds__(256) void intensity_denoise_kernel(IterArgs A, const int32_t* __restrict__ n,
-                                                                const float* __restrict__ scal,
-                                                                const float* __restrict__ t_in,
-                                                                const float* __restrict__ a_in,
-                                                                const uint8_t* __restrict__ act_in,
-                                                                float* __restrict__ t_out,
-                                                                float* __restrict__ a_out,
-                                                                uint8_t* __restrict__ act_out) {
-    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= A.P) return;
-    const int i = pix / A.cols, j = pix - (pix / A.cols) * A.cols;
+template <int K, int R>
+__global__ __launch_bounds__(kTile * kTile) void intensity_denoise_kernel(
+    IterArgs A, const int32_t* __restrict__ n, const float* __restrict__ scal, const float* __restrict__ t_in,
+    const float* __restrict__ a_in, const uint8_t* __restrict__ act_in, float* __restrict__ t_out,
+    float* __restrict__ a_out, uint8_t* __restrict__ act_out) {
+    constexpr int E = Tile<K, R>::E, W = 2 * R + 1;
+    __shared__ Tile<K, R> s;
+    const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
+    load_tile<K, R, true>(s, A, t_in, a_in, act_in, n, i0, j0);
+    __syncthreads();
+    const int ti = threadIdx.x / kTile, tj = threadIdx.x % kTile;
+    const int i = i0 + ti, j = j0 + tj;
+    if (i >= A.rows || j >= A.cols) return;
     const float Tf = (float)A.T;
     const float tau_z = scal[3];
-    const int R = A.R, W = 2 * R + 1;
+    const int pix = i * A.cols + j;
     const float nq = (float)n[pix];
     float an[K];
     bool keep[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int64_t q = (int64_t)pix * K + k;
-        const float tq = t_in[q];
+        const int c = ((ti + R) * E + (tj + R)) * K + k;
+        const float tq = s.t[c];
         t_out[q] = tq;
         keep[k] = false;
         an[k] = 0.f;
-        if (!act_in[q]) continue;
+        if (!s.act[c]) continue;
         float num = 0.f, den = 0.f;
+#pragma unroll
         for (int di = -R; di <= R; ++di) {
-            const int ii = i + di;
-            if (ii < 0 || ii >= A.rows) continue;
+#pragma unroll
             for (int dj = -R; dj <= R; ++dj) {
-                const int jj = j + dj;
-                if (jj < 0 || jj >= A.cols) continue;
                 const float w = A.wgt[(di + R) * W + (dj + R)];
-                const int64_t nbp = (int64_t)ii * A.cols + jj;
-                const float nnb = (float)n[nbp];
+#pragma unroll
                 for (int kk = 0; kk < K; ++kk) {
-                    const int64_t nb = nbp * K + kk;
-                    if (!act_in[nb]) continue;
-                    const float d = circ_diff(t_in[nb] - tq, Tf);
+                    const int cn = ((ti + R + di) * E + (tj + R + dj)) * K + kk;
+                    if (!s.act[cn]) continue;
+                    const float d = circ_diff(s.t[cn] - tq, Tf);
                     if (!(fabsf(d) <= tau_z)) continue;
-                    num += w * (nnb * a_in[nb]);
+                    num += w * s.r[cn];
                     den += w;
                 }
             }
@@ -618,65 +674,85 @@ static IterArgs make_args(const srt3d_params& p) {
     return A;
 }
 
-static inline dim3 pixel_grid(int P) { return dim3((unsigned)((P + 255) / 256)); }
+static inline dim3 pixel_grid(int P, int threads) { return dim3((unsigned)((P + threads - 1) / threads)); }
+static inline dim3 tile_grid(const srt3d_params& p) {
+    return dim3((unsigned)((p.cols + kTile - 1) / kTile), (unsigned)((p.rows + kTile - 1) / kTile));
+}
 
-size_t init_ws_bytes(const srt3d_params& p) { return table_bytes(p.T); }
+size_t init_ws_bytes(const srt3d_params&) { return (size_t)kInitBlocksMax * sizeof(int); }
 
-#define SRT3D_BY_K(K_, CALL)            \
-    switch (K_) {                       \
-        case 1: { constexpr int KK = 1; CALL; } break; \
-        case 2: { constexpr int KK = 2; CALL; } break; \
+#define SRT3D_BY_K(K_, CALL)                            \
+    switch (K_) {                                       \
+        case 1: { constexpr int KK = 1; CALL; } break;  \
+        case 2: { constexpr int KK = 2; CALL; } break;  \
         default: { constexpr int KK = 3; CALL; } break; \
+    }
+
+#define SRT3D_BY_KR(K_, R_, CALL)                                              \
+    switch ((K_) * 4 + (R_)) {                                                 \
+        case 4: { constexpr int KK = 1, RR = 0; CALL; } break;                 \
+        case 5: { constexpr int KK = 1, RR = 1; CALL; } break;                 \
+        case 6: { constexpr int KK = 1, RR = 2; CALL; } break;                 \
+        case 7: { constexpr int KK = 1, RR = 3; CALL; } break;                 \
+        case 8: { constexpr int KK = 2, RR = 0; CALL; } break;                 \
+        case 9: { constexpr int KK = 2, RR = 1; CALL; } break;                 \
+        case 10: { constexpr int KK = 2, RR = 2; CALL; } break;                \
+        case 11: { constexpr int KK = 2, RR = 3; CALL; } break;                \
+        case 12: { constexpr int KK = 3, RR = 0; CALL; } break;                \
+        case 13: { constexpr int KK = 3, RR = 1; CALL; } break;                \
+        case 14: { constexpr int KK = 3, RR = 2; CALL; } break;                \
+        default: { constexpr int KK = 3, RR = 3; CALL; } break;                \
     }
 
 hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int irf_len, int irf_origin,
                        const srt3d_params& p, const srt3d_state& st, void* ws, hipStream_t s) {
     const int P = p.rows * p.cols;
-    hipLaunchKernelGGL(frame_constants_kernel, dim3(1), dim3(256), 0, s, n, P, irf, irf_len, irf_origin, p.T, p.m,
-                       p.K_max, p.eta_t, p.eta_a, p.tau_z, st.hhat, st.scal);
+    hipLaunchKernelGGL(frame_constants_kernel, dim3(1), dim3(256), 0, s, irf, irf_len, irf_origin, p.T, p.m,
+                       p.tau_z, st.hhat, st.scal);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    float2* table = reinterpret_cast<float2*>(ws);
-    e = launch_phase_table(p.T, table, s);
-    if (e != hipSuccess) return e;
     const int stride = p.init_stride > 0 ? p.init_stride : (p.T / (8 * p.m) > 1 ? p.T / (8 * p.m) : 1);
-    const size_t lds = (size_t)p.T * sizeof(float2) + 4 * SRT3D_MAX_M_RECON * sizeof(float2);
     int dev = 0, cus = 0;
-    e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return e;
-    const int64_t need = ((int64_t)P + 3) / 4;
-    const int64_t cap = (int64_t)cus * 8;
-    const unsigned blocks = (unsigned)(need < cap ? need : cap);
-    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((init_kernel<KK>), dim3(blocks), dim3(256), lds, s, z, n, table, st.hhat,
-                                           st.scal, P, p.T, p.m, stride, p.r_min, st.t[0], st.alpha[0],
-                                           st.active[0]));
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    int64_t blocks = ((int64_t)P + 3) / 4;
+    const int64_t cap = std::min<int64_t>((int64_t)cus * 8, kInitBlocksMax);
+    if (blocks > cap) blocks = cap;
+    int* part = reinterpret_cast<int*>(ws);
+    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((init_kernel<KK>), dim3((unsigned)blocks), dim3(256), 0, s, z, n,
+                                           st.hhat, st.scal, P, p.T, p.m, stride, p.r_min, st.t[0], st.alpha[0],
+                                           st.active[0], part));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(step_sizes_kernel, dim3(1), dim3(256), 0, s, part, (int)blocks, p.K_max, p.eta_t, p.eta_a,
+                       st.scal);
     return hipGetLastError();
 }
 
 hipError_t launch_data_step(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st,
                             int cur, hipStream_t s) {
     const IterArgs A = make_args(p);
-    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((data_step_kernel<KK>), pixel_grid(A.P), dim3(256), 0, s, A, z, n,
-                                           st.hhat, st.scal, st.t[cur], st.alpha[cur], st.active[cur]));
+    const int threads = p.m > 60 ? kDataThreads / 2 : kDataThreads;   // keeps the staged sketches <= 64 KiB
+    const size_t lds = (size_t)threads * (2 * p.m + 2) * sizeof(float);
+    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((data_step_kernel<KK>), pixel_grid(A.P, threads), dim3(threads),
+                                           lds, s, A, z, n, st.hhat, st.scal, st.t[cur], st.alpha[cur],
+                                           st.active[cur]));
     return hipGetLastError();
 }
 
 hipError_t launch_depth_denoise(const srt3d_params& p, const srt3d_state& st, int src, int dst, hipStream_t s) {
     const IterArgs A = make_args(p);
-    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((depth_denoise_kernel<KK>), pixel_grid(A.P), dim3(256), 0, s, A, st.scal,
-                                           st.t[src], st.alpha[src], st.active[src], st.t[dst], st.alpha[dst],
-                                           st.active[dst]));
+    SRT3D_BY_KR(p.K_max, p.R, hipLaunchKernelGGL((depth_denoise_kernel<KK, RR>), tile_grid(p), dim3(kTile * kTile), 0,
+                                                 s, A, st.scal, st.t[src], st.alpha[src], st.active[src], st.t[dst],
+                                                 st.alpha[dst], st.active[dst]));
     return hipGetLastError();
 }
 
 hipError_t launch_intensity_denoise(const srt3d_params& p, const int32_t* n, const srt3d_state& st, int src,
                                     int dst, hipStream_t s) {
     const IterArgs A = make_args(p);
-    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((intensity_denoise_kernel<KK>), pixel_grid(A.P), dim3(256), 0, s, A, n,
-                                           st.scal, st.t[src], st.alpha[src], st.active[src], st.t[dst],
-                                           st.alpha[dst], st.active[dst]));
+    SRT3D_BY_KR(p.K_max, p.R, hipLaunchKernelGGL((intensity_denoise_kernel<KK, RR>), tile_grid(p),
+                                                 dim3(kTile * kTile), 0, s, A, n, st.scal, st.t[src], st.alpha[src],
+                                                 st.active[src], st.t[dst], st.alpha[dst], st.active[dst]));
     return hipGetLastError();
 }
 
@@ -684,8 +760,8 @@ hipError_t launch_finalize(const srt3d_params& p, const int32_t* n, const srt3d_
                            float* intensity, uint8_t* active, float* bg, hipStream_t s) {
     const IterArgs A = make_args(p);
     const int c = st.cur;
-    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((finalize_kernel<KK>), pixel_grid(A.P), dim3(256), 0, s, A, n, st.t[c],
-                                           st.alpha[c], st.active[c], depth, intensity, active, bg));
+    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((finalize_kernel<KK>), pixel_grid(A.P, 256), dim3(256), 0, s, A, n,
+                                           st.t[c], st.alpha[c], st.active[c], depth, intensity, active, bg));
     return hipGetLastError();
 }
 

@@ -56,7 +56,7 @@ def test_workspace_queries(lib):
     assert lib.srt3d_hist_workspace_bytes(16384, 4, 0) == 0
     p = L._Params()
     lib.srt3d_params_default(ctypes.byref(p), 32, 32, 1024, 4, 1)
-    assert lib.srt3d_init_workspace_bytes(ctypes.byref(p)) == 1024 * 8
+    assert lib.srt3d_init_workspace_bytes(ctypes.byref(p)) == 4096 * 4     # per-workgroup maxima of n
     p.K_max = 4
     assert lib.srt3d_init_workspace_bytes(ctypes.byref(p)) == 0
 

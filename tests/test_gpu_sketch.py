@@ -24,10 +24,14 @@ def test_phase_table_is_rounded_fp64():
         _print_case(test="phase_table", T=T)
         tab = srt.phase_table(T, dev).cpu().numpy()
         k = np.arange(T)
-        ref = np.stack([np.cos(2 * np.pi * k / T), np.sin(2 * np.pi * k / T)], 1).astype(np.float32)
-        diff = tab.view(np.int32).astype(np.int64) - ref.view(np.int32).astype(np.int64)
-        assert np.max(np.abs(diff)) <= 1                      # never more than 1 ulp
-        assert np.count_nonzero(diff) <= max(1, T // 10000)   # and essentially always exact
+        ref = np.stack([np.cos(2 * np.pi * k / T), np.sin(2 * np.pi * k / T)], 1)
+        quarter = (4 * k) % T == 0           # exact values at multiples of pi/2 (FP64 cos/sin of a
+        ref[quarter] = np.rint(ref[quarter])  # rounded 2 pi k / T leave ~1e-16 there)
+        ref = ref.astype(np.float32)
+        differ = tab != ref                                   # +0 and -0 compare equal
+        ulps = np.abs(tab.view(np.int32).astype(np.int64) - ref.view(np.int32).astype(np.int64))
+        assert np.all(ulps[differ] <= 1)                      # never more than 1 ulp
+        assert np.count_nonzero(differ) <= max(1, T // 10000)  # and essentially always exact
 
 
 def test_phase_indices_bit_exact():
@@ -132,7 +136,8 @@ def test_long_exposure_chunks_equal_whole():
     S, nr = OS.sketch_sums(st_np, off_np, T, m)
     np.testing.assert_array_equal(nacc.cpu().numpy(), nr)
     accc = acc.cpu().numpy()
-    np.testing.assert_allclose(accc[..., 0] + 1j * accc[..., 1], S, atol=1e-5 * np.sqrt(np.maximum(nr, 1))[:, None])
+    ratio = np.abs(accc[..., 0] + 1j * accc[..., 1] - S) / (1e-5 * np.sqrt(np.maximum(nr, 1))[:, None])
+    assert np.max(ratio) <= 1.0, np.max(ratio)
 
 
 def test_throughput_frame_sampled_pixels():
@@ -180,7 +185,12 @@ def test_hist_sketch_matches_oracle(precision, m):
 
 @pytest.mark.parametrize("precision", ["fp16x2", "bf16x3"])
 def test_hist_hi_counts_path(precision):
-    """Counts at and above 2^8 / 2^11 exercise the exact hi/lo split of the 16-bit forms."""
+    """Counts at and above 2^8 / 2^11 exercise the exact hi/lo split of the 16-bit forms.
+
+    These pixels hold 1.5e4..6.6e4 counts, where 1e-5 n^-1/2 (< 8e-8) is below what FP32
+    accumulation of n unit-size terms delivers, so an absolute floor of 2.5e-7 applies:
+    the FP16 pair represents F to 2^-23 and each of the T/32 FP32 partial-sum additions
+    rounds at 2^-24 of n."""
     dev = device()
     rng = np.random.default_rng(4)
     P, T, m = 100, 256, 8
@@ -193,7 +203,8 @@ def test_hist_hi_counts_path(precision):
     torch.cuda.synchronize()
     zr, nr = OS.sketch_hist(H, m)
     np.testing.assert_array_equal(n.cpu().numpy(), nr)
-    bad, _, _ = sketch_violations(to_complex(z), zr, nr)
+    bad, err, _ = sketch_violations(to_complex(z), zr, nr, abs_floor=2.5e-7)
+    print(precision, "max abs error", float(err.max()))
     assert not bad.any()
 
 
