@@ -139,9 +139,16 @@ int srt3d_iterate(srt3d_state* st, const float* d_z, const int32_t* d_n, const s
     if (rc != SRT3D_OK) return rc;
     if ((rc = check_state(st)) != SRT3D_OK) return rc;
     if (!d_z || !d_n || iters < 0) return SRT3D_EINVAL;
-    for (int it = 0; it < iters; ++it)
-        for (int stage = 0; stage < 3; ++stage)
-            if ((rc = srt3d_step(st, d_z, d_n, p, stage, stream)) != SRT3D_OK) return rc;
+    if (iters == 0) return SRT3D_OK;
+    // data step, then one fused launch per iteration: depth and intensity denoisers of
+    // iteration it and the data step of iteration it + 1 (none after the last)
+    hipStream_t s = as_stream(stream);
+    if (launch_data_step(*p, d_z, d_n, *st, st->cur, s) != hipSuccess) return SRT3D_EDEVICE;
+    for (int it = 0; it < iters; ++it) {
+        const int c = st->cur;
+        if (launch_iteration(*p, d_z, d_n, *st, c, 1 - c, it + 1 < iters, s) != hipSuccess) return SRT3D_EDEVICE;
+        st->cur = 1 - c;
+    }
     return SRT3D_OK;
 }
 

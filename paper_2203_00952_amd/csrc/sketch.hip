@@ -1,9 +1,11 @@
 // Photon sketch, Section 2, eq. (3):  z_l = (1/n) sum_p exp(i w_l x_p),  w_l = 2 pi l / T.
 //
 // Design (gfx950):
-//  * The phase w_l x_p is reduced exactly: k_l = (l x_p) mod T is advanced by one integer add
-//    and a wrap per harmonic, and (cos, sin)(2 pi k / T) is read from a T-entry float2 table
-//    held in LDS (loaded once per persistent workgroup).  No transcendental runs per photon.
+//  * The phase w_l x_p is reduced exactly: k_l = (l x_p) mod T is advanced by integer adds and
+//    a wrap, and (cos, sin)(2 pi k / T) is read from a T-entry float2 table held in LDS (loaded
+//    once per persistent workgroup).  Odd harmonics are table reads; each even harmonic is the
+//    preceding entry times exp(i w_1 x) (one complex multiply), halving the LDS reads.  No
+//    transcendental runs per photon.
 //  * A group of G lanes owns one pixel; its lanes stride through the pixel's stamps, so each
 //    wave load is G contiguous int32 per pixel (coalesced).  Each lane keeps 2*MC FP32 partial
 //    sums (MC harmonics per pass; m is split into power-of-two passes <= 32).
@@ -73,13 +75,18 @@ __device__ __forceinline__ void reduce_scatter(float* v, int lane, int& base) {
     }
 }
 
-// One pass over a pixel's photons for harmonics l0+1 .. l0+MC.
+// One pass over a pixel's photons for harmonics l0+1 .. l0+MC.  Harmonics come in pairs: the
+// first of each pair is read from the table at its exact phase k = (l x) mod T (advanced by 2x
+// per pair), the second is that entry times exp(i w_1 x), the table entry at k = x, so each
+// photon costs MC/2 table reads (LDS bandwidth, with its data-dependent bank conflicts, is the
+// binding resource) and two extra multiply-adds per pair.
 template <int MC, int G, bool POW2>
 __device__ __forceinline__ void sketch_pass(const int32_t* __restrict__ stamps, int64_t b, int64_t e, int lane,
                                             int l0, int T, uint32_t T8, const float2* s_table, int64_t count,
                                             int64_t count_total, float* __restrict__ zrow,
                                             double* __restrict__ accrow, int& bad) {
     constexpr int V = 2 * MC;
+    const char* tab = reinterpret_cast<const char*>(s_table);
     float v[V];
 #pragma unroll
     for (int i = 0; i < V; ++i) v[i] = 0.f;
@@ -91,17 +98,32 @@ __device__ __forceinline__ void sketch_pass(const int32_t* __restrict__ stamps, 
             if (l0 == 0) ++bad;
         }
         const uint32_t x8 = (uint32_t)x << 3;
-        uint32_t k8 = 0;
-        if (l0 != 0) {
-            const uint32_t lx = (uint32_t)l0 * (uint32_t)x;
-            k8 = (POW2 ? (lx & (uint32_t)(T - 1)) : (lx % (uint32_t)T)) << 3;
-        }
+        if constexpr (MC == 1) {
+            uint32_t k8 = x8;
+            if (l0 != 0) {
+                const uint32_t lx = (uint32_t)(l0 + 1) * (uint32_t)x;
+                k8 = (POW2 ? (lx & (uint32_t)(T - 1)) : (lx % (uint32_t)T)) << 3;
+            }
+            const float2 c = *reinterpret_cast<const float2*>(tab + k8);
+            v[0] += c.x;
+            v[1] += c.y;
+        } else {
+            const float2 u1 = *reinterpret_cast<const float2*>(tab + x8);   // exp(i w_1 x)
+            const uint32_t x8x2 = phase_advance<POW2>(x8, x8, T8);            // 2x mod T
+            uint32_t k8 = x8;                                                  // phase of l0 + 1
+            if (l0 != 0) {
+                const uint32_t lx = (uint32_t)(l0 + 1) * (uint32_t)x;
+                k8 = (POW2 ? (lx & (uint32_t)(T - 1)) : (lx % (uint32_t)T)) << 3;
+            }
 #pragma unroll
-        for (int j = 0; j < MC; ++j) {
-            k8 = phase_advance<POW2>(k8, x8, T8);
-            const float2 c = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(s_table) + k8);
-            v[2 * j] += c.x;
-            v[2 * j + 1] += c.y;
+            for (int j = 0; j < MC; j += 2) {
+                const float2 c = (j == 0 && l0 == 0) ? u1 : *reinterpret_cast<const float2*>(tab + k8);
+                v[2 * j] += c.x;
+                v[2 * j + 1] += c.y;
+                v[2 * j + 2] += c.x * u1.x - c.y * u1.y;                    // next harmonic: c * u1
+                v[2 * j + 3] += c.x * u1.y + c.y * u1.x;
+                k8 = phase_advance<POW2>(k8, x8x2, T8);
+            }
         }
     }
     int base = 0;

@@ -27,7 +27,6 @@ constexpr int kMaxW = (2 * SRT3D_MAX_R + 1) * (2 * SRT3D_MAX_R + 1);
 constexpr float kCholEps = 1e-5f;    // pivot <= kCholEps * trace counts as singular
 constexpr int kTile = 16;            // denoiser tile edge (pixels)
 constexpr int kInitBlocksMax = 4096; // init workgroups (bounds the partial-max buffer)
-constexpr int kDataThreads = 128;    // pixels per data-step workgroup (64 when m > 60)
 
 struct IterArgs {
     int rows, cols, P, T, m, K, R, Rb;
@@ -36,36 +35,49 @@ struct IterArgs {
 };
 
 // ----------------------------------------------------------------------------- helpers
+// Map t onto [0, T).  Steps move t by much less than T, so one add or subtract is the usual
+// path; FP32 rounding of t + T onto T is mapped to 0.
 __device__ __forceinline__ float wrap_t(float t, float Tf) {
-    float r = t - Tf * floorf(t / Tf);
-    if (r >= Tf) r -= Tf;
-    if (r < 0.f) r += Tf;
-    if (r >= Tf) r = 0.f;
+    if (t < 0.f) t += Tf;
+    else if (t >= Tf) t -= Tf;
+    if (!(t >= 0.f && t < Tf)) {
+        t = t - Tf * floorf(t / Tf);
+        if (!(t >= 0.f && t < Tf)) t = 0.f;
+    }
+    return t;
+}
+
+// Signed circular difference in (-T/2, T/2] of d = a - b with a, b in [0, T).
+__device__ __forceinline__ float circ_diff(float d, float Tf) {
+    const float h = 0.5f * Tf;
+    if (d > h) d -= Tf;
+    else if (d <= -h) d += Tf;
+    return d;
+}
+
+// a mod T for 0 <= a < 2^24 (exact: the float quotient is off by at most one).
+__device__ __forceinline__ int mod_small(int a, int T, float invT) {
+    const int q = (int)((float)a * invT);
+    int r = a - q * T;
+    if (r < 0) r += T;
+    else if (r >= T) r -= T;
     return r;
 }
 
-__device__ __forceinline__ float circ_diff(float d, float Tf) {
-    float r = wrap_t(d, Tf);
-    return r > 0.5f * Tf ? r - Tf : r;
-}
-
-// exp(i 2 pi k / T) for an integer phase k in [0, 2T).
-__device__ __forceinline__ float2 phasor_int(int k, int T) {
+// exp(i 2 pi k / T) for an integer phase k in [0, T).
+__device__ __forceinline__ float2 phasor_int(int k, float twoinvT) {
     float s, c;
-    sincospif((2.0f * (float)k) / (float)T, &s, &c);
+    sincospif((float)k * twoinvT, &s, &c);
     return make_float2(c, s);
 }
 
-// exp(i w_l t) with the phase (l t) mod T reduced through the integer part of t.
-__device__ __forceinline__ float2 phasor(int l, float t, int T) {
+// exp(i w_l t), t in [0, T): the phase (l t) mod T is reduced through the integer part of t.
+__device__ __forceinline__ float2 phasor(int l, float t, int T, float invT, float twoinvT) {
     const float ft = floorf(t);
-    const int it = (int)ft;
-    const float fr = t - ft;
-    const int k = (int)(((int64_t)l * it) % T);
-    const float ph = (float)k + (float)l * fr;
-    const float x = (2.0f * ph) / (float)T;
+    const int k = mod_small(l * (int)ft, T, invT);
+    const float ph = (float)k + (float)l * (t - ft);
     float s, c;
-    sincospif(x, &s, &c);
+    sincospif(ph * twoinvT, &s, &c);
     return make_float2(c, s);
 }
 
@@ -195,6 +207,7 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
     const int wv = threadIdx.x >> 6;
     const int G = (T + stride - 1) / stride;
     const float e2 = scal[4];
+    const float invT = 1.0f / (float)T, twoinvT = 2.0f / (float)T;
     const int waves_total = gridDim.x * (blockDim.x >> 6);
     int nmax = 0;
     const float2 hl = lane < m ? reinterpret_cast<const float2*>(hhat)[lane] : make_float2(0.f, 0.f);
@@ -227,7 +240,7 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
                 float c = 0.f;
                 for (int l = 0; l < m; ++l) {
                     if ((l & 15) == 0) {           // exact anchor: phase ((l+1) tau) mod T
-                        u = phasor_int((int)(((int64_t)(l + 1) * tg) % T), T);
+                        u = phasor_int(mod_small((l + 1) * tg, T, invT), twoinvT);
                         if (l == 0) u1 = u;
                     } else {
                         u = cmul(u, u1);
@@ -254,7 +267,7 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
             tau[k] = tk;
             amp[k] = a;
             if (lane < m) {                        // w_l -= a hhat_l exp(i w_l tau)
-                const float2 g = cmul(hl, phasor_int((int)(((int64_t)(lane + 1) * tk) % T), T));
+                const float2 g = cmul(hl, phasor_int(mod_small((lane + 1) * tk, T, invT), twoinvT));
                 wl.x -= a * g.x;
                 wl.y -= a * g.y;
             }
@@ -303,25 +316,34 @@ __global__ __launch_bounds__(256) void step_sizes_kernel(const int* __restrict__
 }
 
 // ----------------------------------------------------------------------------- data step
+// Four lanes per pixel: lane `sub` takes harmonics l in (lo, hi], a contiguous quarter of 1..m,
+// reads its slice of the pixel's sketch directly (the four lanes cover the row contiguously)
+// and keeps a phasor recurrence re-anchored at the start of its slice and every 8 harmonics.
+// Partial gradient sums are combined over the four lanes, which then apply identical updates.
+constexpr int kLanesPerPixel = 4;
+
 template <int K>
-__device__ __forceinline__ void residual_pass(const float2* __restrict__ zs, const float2* __restrict__ hp, int m, int T,
-                                              const float* tk, const float* ak, const bool* on, float* gsum,
-                                              bool depth) {
+__device__ __forceinline__ void residual_pass(const float2* __restrict__ zp, const float2* __restrict__ hp, int lo,
+                                              int hi, int T, float invT, float twoinvT, const float* tk,
+                                              const float* ak, const bool* on, float* gsum, bool depth) {
     float2 u[K], u1[K];
-    const float w1 = 6.283185307179586f / (float)T;
-    for (int l = 1; l <= m; ++l) {
-        const float2 h = hp[l - 1];
-        const float2 zl = zs[l - 1];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        u1[k] = on[k] ? phasor(1, tk[k], T, invT, twoinvT) : make_float2(1.f, 0.f);
+        u[k] = u1[k];
+    }
+    const float w1 = 6.283185307179586f * invT;
+    for (int l0 = lo; l0 < hi; ++l0) {           // harmonic l = l0 + 1
+        const int l = l0 + 1;
+        const float2 h = hp[l0];
+        const float2 zl = zp[l0];
         float2 g[K];
         float2 e = make_float2(-zl.x, -zl.y);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (!on[k]) continue;
-            if (l == 1) {
-                u1[k] = phasor(1, tk[k], T);
-                u[k] = u1[k];
-            } else if ((l & 7) == 1) {
-                u[k] = phasor(l, tk[k], T);
+            if (l0 == lo || ((l0 - lo) & 7) == 0) {
+                if (l > 1) u[k] = phasor(l, tk[k], T, invT, twoinvT);
             } else {
                 u[k] = cmul(u[k], u1[k]);
             }
@@ -340,29 +362,49 @@ __device__ __forceinline__ void residual_pass(const float2* __restrict__ zs, con
                 if (on[k]) gsum[k] += e.x * g[k].x + e.y * g[k].y;
         }
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        gsum[k] += __shfl_xor(gsum[k], 1, 64);
+        gsum[k] += __shfl_xor(gsum[k], 2, 64);
+    }
+}
+
+// One data step for the K points of a pixel, by the four lanes `sub` = 0..3 of the pixel.
+template <int K>
+__device__ __forceinline__ void data_point(const float* __restrict__ z, const float* __restrict__ hhat, int pix,
+                                           int sub, int m, int T, float nn, float gam_t, float gam_a, float* tk,
+                                           float* ak, const bool* on) {
+    const int lo = (sub * m) / kLanesPerPixel, hi = ((sub + 1) * m) / kLanesPerPixel;
+    const float Tf = (float)T, invT = 1.0f / Tf, twoinvT = 2.0f / Tf;
+    const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m);
+    const float2* hp = reinterpret_cast<const float2*>(hhat);
+    float gt[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) gt[k] = 0.f;
+    residual_pass<K>(zp, hp, lo, hi, T, invT, twoinvT, tk, ak, on, gt, true);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (on[k]) tk[k] = wrap_t(tk[k] - gam_t * (-2.f * nn * ak[k] * gt[k]), Tf);
+    float ga[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) ga[k] = 0.f;
+    residual_pass<K>(zp, hp, lo, hi, T, invT, twoinvT, tk, ak, on, ga, false);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (on[k]) ak[k] = ak[k] - gam_a * (2.f * nn * ga[k]);
+    project_capped_simplex<K>(ak, on);
 }
 
 template <int K>
-__global__ __launch_bounds__(kDataThreads) void data_step_kernel(IterArgs A, const float* __restrict__ z,
-                                                                 const int32_t* __restrict__ n,
-                                                                 const float* __restrict__ hhat,
-                                                                 const float* __restrict__ scal,
-                                                                 float* __restrict__ t, float* __restrict__ alpha,
-                                                                 const uint8_t* __restrict__ active) {
-    extern __shared__ float s_z[];                 // [blockDim.x][2m + 2]
-    const int m = A.m, rs = 2 * m + 2;
-    const int nt = blockDim.x;
-    const int64_t p0 = (int64_t)blockIdx.x * nt;
-    const int npx = (int)min((int64_t)nt, (int64_t)A.P - p0);
-    // coalesced staging of the workgroup's sketches
-    const float* zb = z + p0 * 2 * m;
-    for (int i = threadIdx.x; i < npx * 2 * m; i += nt) {
-        const int r = i / (2 * m), c = i - r * (2 * m);
-        s_z[r * rs + c] = zb[i];
-    }
-    __syncthreads();
-    const int pix = (int)p0 + threadIdx.x;
-    if (threadIdx.x >= npx) return;
+__global__ __launch_bounds__(256) void data_step_kernel(IterArgs A, const float* __restrict__ z,
+                                                        const int32_t* __restrict__ n,
+                                                        const float* __restrict__ hhat,
+                                                        const float* __restrict__ scal, float* __restrict__ t,
+                                                        float* __restrict__ alpha,
+                                                        const uint8_t* __restrict__ active) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int pix = gid / kLanesPerPixel, sub = gid % kLanesPerPixel;
+    if (pix >= A.P) return;                      // the four lanes of a pixel leave together
     float tk[K], ak[K];
     bool on[K];
     bool any = false;
@@ -374,27 +416,8 @@ __global__ __launch_bounds__(kDataThreads) void data_step_kernel(IterArgs A, con
         any |= on[k];
     }
     if (!any) return;
-    const float nn = (float)n[pix];
-    const float gam_t = scal[1], gam_a = scal[2];
-    const float Tf = (float)A.T;
-    const float2* zs = reinterpret_cast<const float2*>(s_z + threadIdx.x * rs);
-    const float2* hp = reinterpret_cast<const float2*>(hhat);
-
-    float gt[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) gt[k] = 0.f;
-    residual_pass<K>(zs, hp, m, A.T, tk, ak, on, gt, true);
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-        if (on[k]) tk[k] = wrap_t(tk[k] - gam_t * (-2.f * nn * ak[k] * gt[k]), Tf);
-    float ga[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) ga[k] = 0.f;
-    residual_pass<K>(zs, hp, m, A.T, tk, ak, on, ga, false);
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-        if (on[k]) ak[k] = ak[k] - gam_a * (2.f * nn * ga[k]);
-    project_capped_simplex<K>(ak, on);
+    data_point<K>(z, hhat, pix, sub, A.m, A.T, (float)n[pix], scal[1], scal[2], tk, ak, on);
+    if (sub != 0) return;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         t[(int64_t)pix * K + k] = tk[k];
@@ -444,23 +467,99 @@ __device__ __forceinline__ bool chol_x0(const float (&M)[4][4], const float (&b)
     return true;
 }
 
-// Tile of (kTile + 2R)^2 pixels x K points in LDS.  Points outside the frame are inactive.
-template <int K, int R>
-struct Tile {
-    static constexpr int E = kTile + 2 * R;
-    float t[E * E * K];
-    float r[E * E * K];       // n * alpha (intensity denoiser only)
-    uint8_t act[E * E * K];
-};
+// Window weight (1 - (di^2 + dj^2) / (R+1)^2)^4 in FP64, rounded once to FP32 (compile time).
+template <int R>
+__device__ constexpr float win_weight(int di, int dj) {
+    const double r = 1.0 - (double)(di * di + dj * dj) / (double)((R + 1) * (R + 1));
+    return (float)(r * r * r * r);
+}
 
-template <int K, int R, bool WITH_R>
-__device__ __forceinline__ void load_tile(Tile<K, R>& s, const IterArgs& A, const float* __restrict__ t_in,
-                                          const float* __restrict__ a_in, const uint8_t* __restrict__ act_in,
-                                          const int32_t* __restrict__ n, int i0, int j0) {
-    constexpr int E = Tile<K, R>::E;
-    for (int idx = threadIdx.x; idx < E * E * K; idx += kTile * kTile) {
+// Depth denoiser for point k of the pixel at LDS cell (ci, cj); t and act are (E x E cells) x K
+// arrays whose window cells lie within the array.  Returns the new depth.
+template <int K, int R>
+__device__ __forceinline__ float dd_point(const float* st, const uint8_t* sa, int E, int ci, int cj, int k, float Tf,
+                                          float tau_z, float lambda_z) {
+    const float tq = st[(ci * E + cj) * K + k];
+    // gated weighted moments; w * phi_r * phi_c are compile-time constants
+    float M[4][4] = {}, b[4] = {};
+#pragma unroll
+    for (int di = -R; di <= R; ++di) {
+#pragma unroll
+        for (int dj = -R; dj <= R; ++dj) {
+            const float w = win_weight<R>(di, dj);
+            const float phi[4] = {1.f, (float)di, (float)dj, (float)(di * di + dj * dj)};
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) {
+                const int cn = ((ci + di) * E + (cj + dj)) * K + kk;
+                const float d = circ_diff(st[cn] - tq, Tf);
+                const bool gate = sa[cn] && fabsf(d) <= tau_z;
+                const float gd = gate ? d : 0.f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    b[r] += (w * phi[r]) * gd;
+#pragma unroll
+                    for (int cc = r; cc < 4; ++cc) M[r][cc] += gate ? w * phi[r] * phi[cc] : 0.f;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int cc = 0; cc < r; ++cc) M[r][cc] = M[cc][r];
+    float a;
+    if (!chol_x0<4>(M, b, a)) {
+        if (!chol_x0<3>(M, b, a)) a = b[0] / (M[0][0] > 0.f ? M[0][0] : 1.f);
+    }
+    return wrap_t(tq + lambda_z * a, Tf);
+}
+
+// Intensity denoiser: gated weighted mean of r = n * alpha around point k of cell (ci, cj).
+template <int K, int R>
+__device__ __forceinline__ float id_mean(const float* st, const uint8_t* sa, const float* sr, int E, int ci, int cj,
+                                         int k, float Tf, float tau_z) {
+    const float tq = st[(ci * E + cj) * K + k];
+    float num = 0.f, den = 0.f;
+#pragma unroll
+    for (int di = -R; di <= R; ++di) {
+#pragma unroll
+        for (int dj = -R; dj <= R; ++dj) {
+            const float w = win_weight<R>(di, dj);
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) {
+                const int cn = ((ci + di) * E + (cj + dj)) * K + kk;
+                const float d = circ_diff(st[cn] - tq, Tf);
+                const bool gate = sa[cn] && fabsf(d) <= tau_z;
+                num += gate ? w * sr[cn] : 0.f;
+                den += gate ? w : 0.f;
+            }
+        }
+    }
+    return num / (den > 0.f ? den : 1.f);
+}
+
+// New alpha and activity of a pixel's K points from their gated means rt (eq. 1 projection).
+template <int K>
+__device__ __forceinline__ void id_update(const float* rt, const bool* was_on, float nq, float r_min, float* an,
+                                          bool* keep) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        keep[k] = was_on[k] && rt[k] >= r_min;
+        an[k] = keep[k] ? rt[k] / (nq > 0.f ? nq : 1.f) : 0.f;
+    }
+    project_capped_simplex<K>(an, keep);
+}
+
+// Load an (E x E cells) x K region with origin (gi0, gj0) into LDS; cells outside the frame are
+// inactive with depth 0.  With WITH_R the intensity n * alpha is loaded too.
+template <int K, bool WITH_R>
+__device__ __forceinline__ void load_region(float* st, uint8_t* sa, float* sr, int E, int gi0, int gj0,
+                                            const IterArgs& A, const float* __restrict__ t_in,
+                                            const float* __restrict__ a_in, const uint8_t* __restrict__ act_in,
+                                            const int32_t* __restrict__ n) {
+    for (int idx = threadIdx.x; idx < E * E * K; idx += blockDim.x) {
         const int k = idx % K, cell = idx / K;
-        const int gi = i0 - R + cell / E, gj = j0 - R + cell % E;
+        const int gi = gi0 + cell / E, gj = gj0 + cell % E;
         float tv = 0.f, rv = 0.f;
         uint8_t av = 0;
         if (gi >= 0 && gi < A.rows && gj >= 0 && gj < A.cols) {
@@ -469,9 +568,9 @@ __device__ __forceinline__ void load_tile(Tile<K, R>& s, const IterArgs& A, cons
             av = act_in[q];
             if constexpr (WITH_R) rv = (float)n[(int64_t)gi * A.cols + gj] * a_in[q];
         }
-        s.t[idx] = tv;
-        s.act[idx] = av;
-        if constexpr (WITH_R) s.r[idx] = rv;
+        st[idx] = tv;
+        sa[idx] = av;
+        if constexpr (WITH_R) sr[idx] = rv;
     }
 }
 
@@ -480,55 +579,24 @@ __global__ __launch_bounds__(kTile * kTile) void depth_denoise_kernel(
     IterArgs A, const float* __restrict__ scal, const float* __restrict__ t_in, const float* __restrict__ a_in,
     const uint8_t* __restrict__ act_in, float* __restrict__ t_out, float* __restrict__ a_out,
     uint8_t* __restrict__ act_out) {
-    constexpr int E = Tile<K, R>::E, W = 2 * R + 1;
-    __shared__ Tile<K, R> s;
+    constexpr int E = kTile + 2 * R;
+    __shared__ float s_t[E * E * K];
+    __shared__ uint8_t s_a[E * E * K];
     const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
-    load_tile<K, R, false>(s, A, t_in, a_in, act_in, nullptr, i0, j0);
+    load_region<K, false>(s_t, s_a, nullptr, E, i0 - R, j0 - R, A, t_in, a_in, act_in, nullptr);
     __syncthreads();
     const int ti = threadIdx.x / kTile, tj = threadIdx.x % kTile;
     const int i = i0 + ti, j = j0 + tj;
     if (i >= A.rows || j >= A.cols) return;
-    const float Tf = (float)A.T;
-    const float tau_z = scal[3];
+    const float Tf = (float)A.T, tau_z = scal[3];
     const int pix = i * A.cols + j;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int64_t q = (int64_t)pix * K + k;
         const int c = ((ti + R) * E + (tj + R)) * K + k;
-        const float tq = s.t[c];
         a_out[q] = a_in[q];
-        act_out[q] = s.act[c];
-        if (!s.act[c]) {
-            t_out[q] = tq;
-            continue;
-        }
-        float M[4][4] = {}, b[4] = {};
-#pragma unroll
-        for (int di = -R; di <= R; ++di) {
-#pragma unroll
-            for (int dj = -R; dj <= R; ++dj) {
-                const float w = A.wgt[(di + R) * W + (dj + R)];
-                const float phi[4] = {1.f, (float)di, (float)dj, (float)(di * di + dj * dj)};
-#pragma unroll
-                for (int kk = 0; kk < K; ++kk) {
-                    const int cn = ((ti + R + di) * E + (tj + R + dj)) * K + kk;
-                    if (!s.act[cn]) continue;
-                    const float d = circ_diff(s.t[cn] - tq, Tf);
-                    if (!(fabsf(d) <= tau_z)) continue;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        b[r] += w * phi[r] * d;
-#pragma unroll
-                        for (int cc = 0; cc < 4; ++cc) M[r][cc] += w * phi[r] * phi[cc];
-                    }
-                }
-            }
-        }
-        float a;
-        if (!chol_x0<4>(M, b, a)) {
-            if (!chol_x0<3>(M, b, a)) a = b[0] / (M[0][0] > 0.f ? M[0][0] : 1.f);
-        }
-        t_out[q] = wrap_t(tq + A.lambda_z * a, Tf);
+        act_out[q] = s_a[c];
+        t_out[q] = s_a[c] ? dd_point<K, R>(s_t, s_a, E, ti + R, tj + R, k, Tf, tau_z, A.lambda_z) : s_t[c];
     }
 }
 
@@ -537,58 +605,126 @@ __global__ __launch_bounds__(kTile * kTile) void intensity_denoise_kernel(
     IterArgs A, const int32_t* __restrict__ n, const float* __restrict__ scal, const float* __restrict__ t_in,
     const float* __restrict__ a_in, const uint8_t* __restrict__ act_in, float* __restrict__ t_out,
     float* __restrict__ a_out, uint8_t* __restrict__ act_out) {
-    constexpr int E = Tile<K, R>::E, W = 2 * R + 1;
-    __shared__ Tile<K, R> s;
+    constexpr int E = kTile + 2 * R;
+    __shared__ float s_t[E * E * K], s_r[E * E * K];
+    __shared__ uint8_t s_a[E * E * K];
     const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
-    load_tile<K, R, true>(s, A, t_in, a_in, act_in, n, i0, j0);
+    load_region<K, true>(s_t, s_a, s_r, E, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
     __syncthreads();
     const int ti = threadIdx.x / kTile, tj = threadIdx.x % kTile;
     const int i = i0 + ti, j = j0 + tj;
     if (i >= A.rows || j >= A.cols) return;
-    const float Tf = (float)A.T;
-    const float tau_z = scal[3];
+    const float Tf = (float)A.T, tau_z = scal[3];
     const int pix = i * A.cols + j;
-    const float nq = (float)n[pix];
-    float an[K];
-    bool keep[K];
+    float rt[K], an[K];
+    bool was[K], keep[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const int64_t q = (int64_t)pix * K + k;
         const int c = ((ti + R) * E + (tj + R)) * K + k;
-        const float tq = s.t[c];
-        t_out[q] = tq;
-        keep[k] = false;
-        an[k] = 0.f;
-        if (!s.act[c]) continue;
-        float num = 0.f, den = 0.f;
+        was[k] = s_a[c] != 0;
+        rt[k] = was[k] ? id_mean<K, R>(s_t, s_a, s_r, E, ti + R, tj + R, k, Tf, tau_z) : 0.f;
+        t_out[(int64_t)pix * K + k] = s_t[c];
+    }
+    id_update<K>(rt, was, (float)n[pix], A.r_min, an, keep);
 #pragma unroll
-        for (int di = -R; di <= R; ++di) {
+    for (int k = 0; k < K; ++k) {
+        a_out[(int64_t)pix * K + k] = an[k];
+        act_out[(int64_t)pix * K + k] = keep[k] ? 1 : 0;
+    }
+}
+
+// One whole iteration for a 16x16 tile: depth denoiser on the tile and an R-pixel ring (the ring
+// is recomputed by each neighbouring tile), intensity denoiser on the tile, then (DS_NEXT) the
+// next iteration's data step.  Input: the state after a data step; output: the state after the
+// next data step (or after the intensity denoiser).  One launch per iteration instead of three.
+template <int K, int R, bool DS_NEXT>
+__global__ __launch_bounds__(kTile * kTile) void iteration_kernel(
+    IterArgs A, const float* __restrict__ z, const int32_t* __restrict__ n, const float* __restrict__ hhat,
+    const float* __restrict__ scal, const float* __restrict__ t_in, const float* __restrict__ a_in,
+    const uint8_t* __restrict__ act_in, float* __restrict__ t_out, float* __restrict__ a_out,
+    uint8_t* __restrict__ act_out) {
+    constexpr int E2 = kTile + 4 * R, E1 = kTile + 2 * R;
+    __shared__ float s_t2[E2 * E2 * K];          // depths after the data step, tile + 2R ring
+    __shared__ uint8_t s_a2[E2 * E2 * K];
+    __shared__ float s_td[E1 * E1 * K];          // depths after the depth denoiser, tile + R ring
+    __shared__ float s_r1[E1 * E1 * K];          // n * alpha after the data step
+    __shared__ uint8_t s_a1[E1 * E1 * K];
+    __shared__ float s_ot[kTile * kTile * K], s_oa[kTile * kTile * K];
+    __shared__ uint8_t s_oo[kTile * kTile * K];
+    const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
+    load_region<K, false>(s_t2, s_a2, nullptr, E2, i0 - 2 * R, j0 - 2 * R, A, t_in, a_in, act_in, nullptr);
+    load_region<K, true>(s_td, s_a1, s_r1, E1, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
+    __syncthreads();
+    const float Tf = (float)A.T, tau_z = scal[3];
+    // depth denoiser on the tile + R ring
+    for (int idx = threadIdx.x; idx < E1 * E1 * K; idx += blockDim.x) {
+        const int k = idx % K, cell = idx / K;
+        const int ci = cell / E1 + R, cj = cell % E1 + R;          // cell in the E2 region
+        const int c2 = (ci * E2 + cj) * K + k;
+        s_td[idx] = s_a2[c2] ? dd_point<K, R>(s_t2, s_a2, E2, ci, cj, k, Tf, tau_z, A.lambda_z) : s_t2[c2];
+    }
+    __syncthreads();
+    // intensity denoiser on the tile
+    const int ti = threadIdx.x / kTile, tj = threadIdx.x % kTile;
+    const int i = i0 + ti, j = j0 + tj;
+    if (i < A.rows && j < A.cols) {
+        float rt[K], an[K];
+        bool was[K], keep[K];
 #pragma unroll
-            for (int dj = -R; dj <= R; ++dj) {
-                const float w = A.wgt[(di + R) * W + (dj + R)];
+        for (int k = 0; k < K; ++k) {
+            const int c = ((ti + R) * E1 + (tj + R)) * K + k;
+            was[k] = s_a1[c] != 0;
+            rt[k] = was[k] ? id_mean<K, R>(s_td, s_a1, s_r1, E1, ti + R, tj + R, k, Tf, tau_z) : 0.f;
+        }
+        id_update<K>(rt, was, (float)n[i * A.cols + j], A.r_min, an, keep);
 #pragma unroll
-                for (int kk = 0; kk < K; ++kk) {
-                    const int cn = ((ti + R + di) * E + (tj + R + dj)) * K + kk;
-                    if (!s.act[cn]) continue;
-                    const float d = circ_diff(s.t[cn] - tq, Tf);
-                    if (!(fabsf(d) <= tau_z)) continue;
-                    num += w * s.r[cn];
-                    den += w;
+        for (int k = 0; k < K; ++k) {
+            const int o = threadIdx.x * K + k;
+            s_ot[o] = s_td[((ti + R) * E1 + (tj + R)) * K + k];
+            s_oa[o] = an[k];
+            s_oo[o] = keep[k] ? 1 : 0;
+        }
+    }
+    if constexpr (DS_NEXT) {
+        __syncthreads();
+        // next data step, four lanes per pixel, 64 pixels per round
+        const int sub = threadIdx.x % kLanesPerPixel;
+        for (int r = 0; r < kLanesPerPixel; ++r) {
+            const int pl = r * (kTile * kTile / kLanesPerPixel) + threadIdx.x / kLanesPerPixel;
+            const int pi = i0 + pl / kTile, pj = j0 + pl % kTile;
+            if (pi >= A.rows || pj >= A.cols) continue;
+            const int pix = pi * A.cols + pj;
+            float tk[K], ak[K];
+            bool on[K], any = false;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                tk[k] = s_ot[pl * K + k];
+                ak[k] = s_oa[pl * K + k];
+                on[k] = s_oo[pl * K + k] != 0;
+                any |= on[k];
+            }
+            if (any) data_point<K>(z, hhat, pix, sub, A.m, A.T, (float)n[pix], scal[1], scal[2], tk, ak, on);
+            if (sub == 0) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int64_t q = (int64_t)pix * K + k;
+                    t_out[q] = tk[k];
+                    a_out[q] = ak[k];
+                    act_out[q] = on[k] ? 1 : 0;
                 }
             }
         }
-        const float rt = num / (den > 0.f ? den : 1.f);
-        if (rt >= A.r_min) {
-            keep[k] = true;
-            an[k] = rt / (nq > 0.f ? nq : 1.f);
-        }
-    }
-    project_capped_simplex<K>(an, keep);
+    } else {
+        if (i < A.rows && j < A.cols) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int64_t q = (int64_t)pix * K + k;
-        a_out[q] = an[k];
-        act_out[q] = keep[k] ? 1 : 0;
+            for (int k = 0; k < K; ++k) {
+                const int64_t q = ((int64_t)i * A.cols + j) * K + k;
+                const int o = threadIdx.x * K + k;
+                t_out[q] = s_ot[o];
+                a_out[q] = s_oa[o];
+                act_out[q] = s_oo[o];
+            }
+        }
     }
 }
 
@@ -731,10 +867,8 @@ hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int 
 hipError_t launch_data_step(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st,
                             int cur, hipStream_t s) {
     const IterArgs A = make_args(p);
-    const int threads = p.m > 60 ? kDataThreads / 2 : kDataThreads;   // keeps the staged sketches <= 64 KiB
-    const size_t lds = (size_t)threads * (2 * p.m + 2) * sizeof(float);
-    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((data_step_kernel<KK>), pixel_grid(A.P, threads), dim3(threads),
-                                           lds, s, A, z, n, st.hhat, st.scal, st.t[cur], st.alpha[cur],
+    const dim3 grid((unsigned)(((int64_t)A.P * kLanesPerPixel + 255) / 256));
+    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((data_step_kernel<KK>), grid, dim3(256), 0, s, A, z, n, st.hhat, st.scal, st.t[cur], st.alpha[cur],
                                            st.active[cur]));
     return hipGetLastError();
 }
@@ -753,6 +887,23 @@ hipError_t launch_intensity_denoise(const srt3d_params& p, const int32_t* n, con
     SRT3D_BY_KR(p.K_max, p.R, hipLaunchKernelGGL((intensity_denoise_kernel<KK, RR>), tile_grid(p),
                                                  dim3(kTile * kTile), 0, s, A, n, st.scal, st.t[src], st.alpha[src],
                                                  st.active[src], st.t[dst], st.alpha[dst], st.active[dst]));
+    return hipGetLastError();
+}
+
+hipError_t launch_iteration(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st, int src,
+                            int dst, bool ds_next, hipStream_t s) {
+    const IterArgs A = make_args(p);
+    if (ds_next) {
+        SRT3D_BY_KR(p.K_max, p.R, hipLaunchKernelGGL((iteration_kernel<KK, RR, true>), tile_grid(p),
+                                                     dim3(kTile * kTile), 0, s, A, z, n, st.hhat, st.scal, st.t[src],
+                                                     st.alpha[src], st.active[src], st.t[dst], st.alpha[dst],
+                                                     st.active[dst]));
+    } else {
+        SRT3D_BY_KR(p.K_max, p.R, hipLaunchKernelGGL((iteration_kernel<KK, RR, false>), tile_grid(p),
+                                                     dim3(kTile * kTile), 0, s, A, z, n, st.hhat, st.scal, st.t[src],
+                                                     st.alpha[src], st.active[src], st.t[dst], st.alpha[dst],
+                                                     st.active[dst]));
+    }
     return hipGetLastError();
 }
 

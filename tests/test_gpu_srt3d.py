@@ -173,6 +173,29 @@ def test_iterations_from_shared_init(make):
     assert ok.mean() >= 0.999
 
 
+@pytest.mark.parametrize("make", [tiny, layered])
+def test_fused_iterations_equal_stage_sequence(make):
+    """srt3d_iterate (one fused launch per iteration) computes what data, depth and intensity
+    stages run one by one compute."""
+    dev = device()
+    fr = make(dev)
+    fr.gpu_init()
+    st0 = _prepared_state(fr)
+    _case(test="fused_vs_stages", P=fr.spec.P, K=fr.K)
+    fr.upload(st0)
+    fr.rec.iterate(fr.z, fr.n, 4)
+    a = fr.download()
+    fr.upload(st0)
+    for _ in range(4):
+        for stage in ("data", "depth", "intensity"):
+            fr.rec.step(stage, fr.z, fr.n)
+    b = fr.download()
+    np.testing.assert_array_equal(a.active, b.active)
+    np.testing.assert_allclose(circ_abs(a.t - b.t, fr.spec.T), 0, atol=1e-4)
+    np.testing.assert_allclose(a.alpha, b.alpha, atol=1e-6)
+    print("bitwise equal:", bool(np.array_equal(a.t, b.t) and np.array_equal(a.alpha, b.alpha)))
+
+
 def test_end_to_end_tiny_with_independent_oracle_sketch():
     """Oracle sketches the stamps itself in FP64 and reconstructs; GPU does everything."""
     dev = device()
