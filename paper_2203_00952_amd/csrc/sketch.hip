@@ -120,8 +120,11 @@ __device__ __forceinline__ void sketch_pass(const int32_t* __restrict__ stamps, 
                 const float2 c = (j == 0 && l0 == 0) ? u1 : *reinterpret_cast<const float2*>(tab + k8);
                 v[2 * j] += c.x;
                 v[2 * j + 1] += c.y;
-                v[2 * j + 2] += c.x * u1.x - c.y * u1.y;                    // next harmonic: c * u1
-                v[2 * j + 3] += c.x * u1.y + c.y * u1.x;
+                // next harmonic: += c * u1, as four fused multiply-adds
+                v[2 * j + 2] = fmaf(c.x, u1.x, v[2 * j + 2]);
+                v[2 * j + 2] = fmaf(-c.y, u1.y, v[2 * j + 2]);
+                v[2 * j + 3] = fmaf(c.x, u1.y, v[2 * j + 3]);
+                v[2 * j + 3] = fmaf(c.y, u1.x, v[2 * j + 3]);
                 k8 = phase_advance<POW2>(k8, x8x2, T8);
             }
         }

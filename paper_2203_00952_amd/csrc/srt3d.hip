@@ -23,7 +23,6 @@
 
 namespace srt3d {
 
-constexpr int kMaxW = (2 * SRT3D_MAX_R + 1) * (2 * SRT3D_MAX_R + 1);
 constexpr float kCholEps = 1e-5f;    // pivot <= kCholEps * trace counts as singular
 constexpr int kTile = 16;            // denoiser tile edge (pixels)
 constexpr int kInitBlocksMax = 4096; // init workgroups (bounds the partial-max buffer)
@@ -31,7 +30,6 @@ constexpr int kInitBlocksMax = 4096; // init workgroups (bounds the partial-max 
 struct IterArgs {
     int rows, cols, P, T, m, K, R, Rb;
     float lambda_z, r_min;
-    float wgt[kMaxW];   // window weights (1 - (di^2 + dj^2) / (R+1)^2)^4, row-major over (di, dj)
 };
 
 // ----------------------------------------------------------------------------- helpers
@@ -47,12 +45,11 @@ __device__ __forceinline__ float wrap_t(float t, float Tf) {
     return t;
 }
 
-// Signed circular difference in (-T/2, T/2] of d = a - b with a, b in [0, T).
-__device__ __forceinline__ float circ_diff(float d, float Tf) {
-    const float h = 0.5f * Tf;
-    if (d > h) d -= Tf;
-    else if (d <= -h) d += Tf;
-    return d;
+// Signed circular difference of d = a - b, a and b in [0, T): d - T * round(d / T), which is d
+// reduced to [-T/2, T/2] (the two ends of that range only differ at |d| = T/2, far outside
+// every depth gate).
+__device__ __forceinline__ float circ_diff(float d, float Tf, float invT) {
+    return fmaf(-Tf, rintf(d * invT), d);
 }
 
 // a mod T for 0 <= a < 2^24 (exact: the float quotient is off by at most one).
@@ -326,11 +323,15 @@ template <int K>
 __device__ __forceinline__ void residual_pass(const float2* __restrict__ zp, const float2* __restrict__ hp, int lo,
                                               int hi, int T, float invT, float twoinvT, const float* tk,
                                               const float* ak, const bool* on, float* gsum, bool depth) {
+    // each lane anchors at the first harmonic of its slice; lane 0 of the pixel's group holds
+    // harmonic 1, whose phasor drives everyone's recurrence
+    const int base = (threadIdx.x & 63) & ~(kLanesPerPixel - 1);
     float2 u[K], u1[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        u1[k] = on[k] ? phasor(1, tk[k], T, invT, twoinvT) : make_float2(1.f, 0.f);
-        u[k] = u1[k];
+        u[k] = on[k] ? phasor(lo + 1, tk[k], T, invT, twoinvT) : make_float2(1.f, 0.f);
+        u1[k].x = __shfl(u[k].x, base, 64);
+        u1[k].y = __shfl(u[k].y, base, 64);
     }
     const float w1 = 6.283185307179586f * invT;
     for (int l0 = lo; l0 < hi; ++l0) {           // harmonic l = l0 + 1
@@ -342,11 +343,7 @@ __device__ __forceinline__ void residual_pass(const float2* __restrict__ zp, con
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (!on[k]) continue;
-            if (l0 == lo || ((l0 - lo) & 7) == 0) {
-                if (l > 1) u[k] = phasor(l, tk[k], T, invT, twoinvT);
-            } else {
-                u[k] = cmul(u[k], u1[k]);
-            }
+            if (l0 > lo) u[k] = ((l0 - lo) & 7) == 0 ? phasor(l, tk[k], T, invT, twoinvT) : cmul(u[k], u1[k]);
             g[k] = cmul(h, u[k]);
             e.x += ak[k] * g[k].x;
             e.y += ak[k] * g[k].y;
@@ -426,79 +423,116 @@ __global__ __launch_bounds__(256) void data_step_kernel(IterArgs A, const float*
 }
 
 // ----------------------------------------------------------------------------- denoisers
-// Solve the leading D x D block of M x = b by Cholesky with the pivot rule; only x[0] is needed.
+// Solve the leading D x D block of M x = b by M = L diag(d) L^T (unit lower L), with
+// reciprocals of the pivots.  The pivot d_j = M_jj - sum_k L_jk^2 d_k is the square of the
+// Cholesky diagonal, so "d_j <= kCholEps * trace" is the Cholesky singularity rule.  Only x[0]
+// is needed.
 template <int D>
-__device__ __forceinline__ bool chol_x0(const float (&M)[4][4], const float (&b)[4], float& x0) {
-    float L[D][D];
+__device__ __forceinline__ bool ldl_x0(const float (&M)[4][4], const float (&b)[4], float& x0) {
+    float L[D][D], d[D], inv[D];
     float tr = 0.f;
 #pragma unroll
     for (int i = 0; i < D; ++i) tr += M[i][i];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
+        float v[D];
         float s = M[j][j];
 #pragma unroll
-        for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+        for (int k = 0; k < j; ++k) {
+            v[k] = L[j][k] * d[k];
+            s -= L[j][k] * v[k];
+        }
         if (!(s > kCholEps * tr)) return false;
-        L[j][j] = sqrtf(s);
+        d[j] = s;
+        inv[j] = __builtin_amdgcn_rcpf(s);
 #pragma unroll
         for (int i = j + 1; i < D; ++i) {
-            float v = M[i][j];
+            float w = M[i][j];
 #pragma unroll
-            for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
-            L[i][j] = v / L[j][j];
+            for (int k = 0; k < j; ++k) w -= L[i][k] * v[k];
+            L[i][j] = w * inv[j];
         }
     }
     float y[D], x[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        float v = b[j];
+        float w = b[j];
 #pragma unroll
-        for (int k = 0; k < j; ++k) v -= L[j][k] * y[k];
-        y[j] = v / L[j][j];
+        for (int k = 0; k < j; ++k) w -= L[j][k] * y[k];
+        y[j] = w;
     }
 #pragma unroll
     for (int j = D - 1; j >= 0; --j) {
-        float v = y[j];
+        float w = y[j] * inv[j];
 #pragma unroll
-        for (int k = j + 1; k < D; ++k) v -= L[k][j] * x[k];
-        x[j] = v / L[j][j];
+        for (int k = j + 1; k < D; ++k) w -= L[k][j] * x[k];
+        x[j] = w;
     }
     x0 = x[0];
     return true;
 }
 
-// Window weight (1 - (di^2 + dj^2) / (R+1)^2)^4 in FP64, rounded once to FP32 (compile time).
+// Integer window weight q = ((R+1)^2 - di^2 - dj^2)^4 = (R+1)^8 w.  The constant factor cancels
+// in the least-squares solution, the pivot rule and the weighted mean, and with integer weights
+// every normal-matrix entry is an integer: exact in FP32 for R <= 2 (largest entry < 2^18).
 template <int R>
-__device__ constexpr float win_weight(int di, int dj) {
-    const double r = 1.0 - (double)(di * di + dj * dj) / (double)((R + 1) * (R + 1));
-    return (float)(r * r * r * r);
+__device__ constexpr float win_q(int di, int dj) {
+    const int64_t u = (int64_t)(R + 1) * (R + 1) - di * di - dj * dj;
+    return (float)(u * u * u * u);
+}
+
+template <int R>
+__device__ constexpr float full_moment(int r, int c) {
+    int64_t acc = 0;
+    for (int di = -R; di <= R; ++di)
+        for (int dj = -R; dj <= R; ++dj) {
+            const int64_t u = (int64_t)(R + 1) * (R + 1) - di * di - dj * dj;
+            const int64_t phi[4] = {1, di, dj, di * di + dj * dj};
+            acc += u * u * u * u * phi[r] * phi[c];
+        }
+    return (float)acc;
 }
 
 // Depth denoiser for point k of the pixel at LDS cell (ci, cj); t and act are (E x E cells) x K
-// arrays whose window cells lie within the array.  Returns the new depth.
+// arrays whose window cells lie within the array.  Returns the new depth.  With one point per
+// pixel and R <= 2 the normal matrix is the full-window sum minus the (few) neighbours that fail
+// the gate -- exact, since all entries are integers below 2^24; otherwise it sums the gated
+// neighbours.  Entries whose factor is zero for a given offset are skipped at compile time.
 template <int K, int R>
 __device__ __forceinline__ float dd_point(const float* st, const uint8_t* sa, int E, int ci, int cj, int k, float Tf,
-                                          float tau_z, float lambda_z) {
+                                          float invT, float tau_z, float lambda_z) {
+    constexpr bool SUB = (K == 1) && (R <= 2);
     const float tq = st[(ci * E + cj) * K + k];
-    // gated weighted moments; w * phi_r * phi_c are compile-time constants
-    float M[4][4] = {}, b[4] = {};
+    float M[4][4], b[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) M[r][c] = SUB ? full_moment<R>(r, c) : 0.f;
 #pragma unroll
     for (int di = -R; di <= R; ++di) {
 #pragma unroll
         for (int dj = -R; dj <= R; ++dj) {
-            const float w = win_weight<R>(di, dj);
-            const float phi[4] = {1.f, (float)di, (float)dj, (float)(di * di + dj * dj)};
+            const float q = win_q<R>(di, dj);
+            const int r2 = di * di + dj * dj;
 #pragma unroll
             for (int kk = 0; kk < K; ++kk) {
                 const int cn = ((ci + di) * E + (cj + dj)) * K + kk;
-                const float d = circ_diff(st[cn] - tq, Tf);
+                const float d = circ_diff(st[cn] - tq, Tf, invT);
                 const bool gate = sa[cn] && fabsf(d) <= tau_z;
-                const float gd = gate ? d : 0.f;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    b[r] += (w * phi[r]) * gd;
-#pragma unroll
-                    for (int cc = r; cc < 4; ++cc) M[r][cc] += gate ? w * phi[r] * phi[cc] : 0.f;
+                const float qd = q * (gate ? d : 0.f);
+                b[0] += qd;
+                if (di != 0) b[1] += (float)di * qd;
+                if (dj != 0) b[2] += (float)dj * qd;
+                if (r2 != 0) b[3] += (float)r2 * qd;
+                if (SUB ? !gate : gate) {
+                    const float sq = SUB ? -q : q;
+                    M[0][0] += sq;
+                    if (di != 0) { M[0][1] += sq * di; M[1][1] += sq * (di * di); }
+                    if (dj != 0) { M[0][2] += sq * dj; M[2][2] += sq * (dj * dj); }
+                    if (di != 0 && dj != 0) M[1][2] += sq * (di * dj);
+                    if (r2 != 0) { M[0][3] += sq * r2; M[3][3] += sq * (r2 * r2); }
+                    if (di != 0 && r2 != 0) M[1][3] += sq * (di * r2);
+                    if (dj != 0 && r2 != 0) M[2][3] += sq * (dj * r2);
                 }
             }
         }
@@ -506,10 +540,10 @@ __device__ __forceinline__ float dd_point(const float* st, const uint8_t* sa, in
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int cc = 0; cc < r; ++cc) M[r][cc] = M[cc][r];
+        for (int c = 0; c < r; ++c) M[r][c] = M[c][r];
     float a;
-    if (!chol_x0<4>(M, b, a)) {
-        if (!chol_x0<3>(M, b, a)) a = b[0] / (M[0][0] > 0.f ? M[0][0] : 1.f);
+    if (!ldl_x0<4>(M, b, a)) {
+        if (!ldl_x0<3>(M, b, a)) a = b[0] * __builtin_amdgcn_rcpf(M[0][0] > 0.f ? M[0][0] : 1.f);
     }
     return wrap_t(tq + lambda_z * a, Tf);
 }
@@ -517,25 +551,25 @@ __device__ __forceinline__ float dd_point(const float* st, const uint8_t* sa, in
 // Intensity denoiser: gated weighted mean of r = n * alpha around point k of cell (ci, cj).
 template <int K, int R>
 __device__ __forceinline__ float id_mean(const float* st, const uint8_t* sa, const float* sr, int E, int ci, int cj,
-                                         int k, float Tf, float tau_z) {
+                                         int k, float Tf, float invT, float tau_z) {
     const float tq = st[(ci * E + cj) * K + k];
     float num = 0.f, den = 0.f;
 #pragma unroll
     for (int di = -R; di <= R; ++di) {
 #pragma unroll
         for (int dj = -R; dj <= R; ++dj) {
-            const float w = win_weight<R>(di, dj);
+            const float w = win_q<R>(di, dj);
 #pragma unroll
             for (int kk = 0; kk < K; ++kk) {
                 const int cn = ((ci + di) * E + (cj + dj)) * K + kk;
-                const float d = circ_diff(st[cn] - tq, Tf);
-                const bool gate = sa[cn] && fabsf(d) <= tau_z;
-                num += gate ? w * sr[cn] : 0.f;
-                den += gate ? w : 0.f;
+                const float d = circ_diff(st[cn] - tq, Tf, invT);
+                const float gw = (sa[cn] && fabsf(d) <= tau_z) ? w : 0.f;
+                num = fmaf(gw, sr[cn], num);
+                den += gw;
             }
         }
     }
-    return num / (den > 0.f ? den : 1.f);
+    return num * __builtin_amdgcn_rcpf(den > 0.f ? den : 1.f);
 }
 
 // New alpha and activity of a pixel's K points from their gated means rt (eq. 1 projection).
@@ -596,7 +630,7 @@ __global__ __launch_bounds__(kTile * kTile) void depth_denoise_kernel(
         const int c = ((ti + R) * E + (tj + R)) * K + k;
         a_out[q] = a_in[q];
         act_out[q] = s_a[c];
-        t_out[q] = s_a[c] ? dd_point<K, R>(s_t, s_a, E, ti + R, tj + R, k, Tf, tau_z, A.lambda_z) : s_t[c];
+        t_out[q] = s_a[c] ? dd_point<K, R>(s_t, s_a, E, ti + R, tj + R, k, Tf, 1.0f / Tf, tau_z, A.lambda_z) : s_t[c];
     }
 }
 
@@ -622,7 +656,7 @@ __global__ __launch_bounds__(kTile * kTile) void intensity_denoise_kernel(
     for (int k = 0; k < K; ++k) {
         const int c = ((ti + R) * E + (tj + R)) * K + k;
         was[k] = s_a[c] != 0;
-        rt[k] = was[k] ? id_mean<K, R>(s_t, s_a, s_r, E, ti + R, tj + R, k, Tf, tau_z) : 0.f;
+        rt[k] = was[k] ? id_mean<K, R>(s_t, s_a, s_r, E, ti + R, tj + R, k, Tf, 1.0f / Tf, tau_z) : 0.f;
         t_out[(int64_t)pix * K + k] = s_t[c];
     }
     id_update<K>(rt, was, (float)n[pix], A.r_min, an, keep);
@@ -636,9 +670,12 @@ __global__ __launch_bounds__(kTile * kTile) void intensity_denoise_kernel(
 // One whole iteration for a 16x16 tile: depth denoiser on the tile and an R-pixel ring (the ring
 // is recomputed by each neighbouring tile), intensity denoiser on the tile, then (DS_NEXT) the
 // next iteration's data step.  Input: the state after a data step; output: the state after the
-// next data step (or after the intensity denoiser).  One launch per iteration instead of three.
+// next data step (or after the intensity denoiser).  One launch per iteration instead of three;
+// 1024 threads per tile so that the data step runs four lanes per pixel in one round.
+constexpr int kIterThreads = kTile * kTile * kLanesPerPixel;
+
 template <int K, int R, bool DS_NEXT>
-__global__ __launch_bounds__(kTile * kTile) void iteration_kernel(
+__global__ __launch_bounds__(kIterThreads) void iteration_kernel(
     IterArgs A, const float* __restrict__ z, const int32_t* __restrict__ n, const float* __restrict__ hhat,
     const float* __restrict__ scal, const float* __restrict__ t_in, const float* __restrict__ a_in,
     const uint8_t* __restrict__ act_in, float* __restrict__ t_out, float* __restrict__ a_out,
@@ -649,56 +686,63 @@ __global__ __launch_bounds__(kTile * kTile) void iteration_kernel(
     __shared__ float s_td[E1 * E1 * K];          // depths after the depth denoiser, tile + R ring
     __shared__ float s_r1[E1 * E1 * K];          // n * alpha after the data step
     __shared__ uint8_t s_a1[E1 * E1 * K];
-    __shared__ float s_ot[kTile * kTile * K], s_oa[kTile * kTile * K];
+    __shared__ float s_oa[kTile * kTile * K];
     __shared__ uint8_t s_oo[kTile * kTile * K];
     const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
     load_region<K, false>(s_t2, s_a2, nullptr, E2, i0 - 2 * R, j0 - 2 * R, A, t_in, a_in, act_in, nullptr);
     load_region<K, true>(s_td, s_a1, s_r1, E1, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
     __syncthreads();
-    const float Tf = (float)A.T, tau_z = scal[3];
+    const float Tf = (float)A.T, invT = 1.0f / Tf, tau_z = scal[3];
     // depth denoiser on the tile + R ring
     for (int idx = threadIdx.x; idx < E1 * E1 * K; idx += blockDim.x) {
         const int k = idx % K, cell = idx / K;
         const int ci = cell / E1 + R, cj = cell % E1 + R;          // cell in the E2 region
         const int c2 = (ci * E2 + cj) * K + k;
-        s_td[idx] = s_a2[c2] ? dd_point<K, R>(s_t2, s_a2, E2, ci, cj, k, Tf, tau_z, A.lambda_z) : s_t2[c2];
+        if (s_a2[c2]) s_td[idx] = dd_point<K, R>(s_t2, s_a2, E2, ci, cj, k, Tf, invT, tau_z, A.lambda_z);
+        else s_td[idx] = s_t2[c2];
     }
     __syncthreads();
-    // intensity denoiser on the tile
-    const int ti = threadIdx.x / kTile, tj = threadIdx.x % kTile;
-    const int i = i0 + ti, j = j0 + tj;
-    if (i < A.rows && j < A.cols) {
-        float rt[K], an[K];
-        bool was[K], keep[K];
+    // intensity denoiser on the tile (one thread per pixel)
+    if (threadIdx.x < kTile * kTile) {
+        const int ti = threadIdx.x / kTile, tj = threadIdx.x % kTile;
+        const int i = i0 + ti, j = j0 + tj;
+        if (i < A.rows && j < A.cols) {
+            float rt[K], an[K];
+            bool was[K], keep[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int c = ((ti + R) * E1 + (tj + R)) * K + k;
-            was[k] = s_a1[c] != 0;
-            rt[k] = was[k] ? id_mean<K, R>(s_td, s_a1, s_r1, E1, ti + R, tj + R, k, Tf, tau_z) : 0.f;
-        }
-        id_update<K>(rt, was, (float)n[i * A.cols + j], A.r_min, an, keep);
+            for (int k = 0; k < K; ++k) {
+                const int c = ((ti + R) * E1 + (tj + R)) * K + k;
+                was[k] = s_a1[c] != 0;
+                rt[k] = was[k] ? id_mean<K, R>(s_td, s_a1, s_r1, E1, ti + R, tj + R, k, Tf, invT, tau_z) : 0.f;
+            }
+            id_update<K>(rt, was, (float)n[i * A.cols + j], A.r_min, an, keep);
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int o = threadIdx.x * K + k;
-            s_ot[o] = s_td[((ti + R) * E1 + (tj + R)) * K + k];
-            s_oa[o] = an[k];
-            s_oo[o] = keep[k] ? 1 : 0;
+            for (int k = 0; k < K; ++k) {
+                const int o = threadIdx.x * K + k;
+                s_oa[o] = an[k];
+                s_oo[o] = keep[k] ? 1 : 0;
+                if constexpr (!DS_NEXT) {
+                    const int64_t q = ((int64_t)i * A.cols + j) * K + k;
+                    t_out[q] = s_td[((ti + R) * E1 + (tj + R)) * K + k];
+                    a_out[q] = an[k];
+                    act_out[q] = keep[k] ? 1 : 0;
+                }
+            }
         }
     }
     if constexpr (DS_NEXT) {
         __syncthreads();
-        // next data step, four lanes per pixel, 64 pixels per round
-        const int sub = threadIdx.x % kLanesPerPixel;
-        for (int r = 0; r < kLanesPerPixel; ++r) {
-            const int pl = r * (kTile * kTile / kLanesPerPixel) + threadIdx.x / kLanesPerPixel;
-            const int pi = i0 + pl / kTile, pj = j0 + pl % kTile;
-            if (pi >= A.rows || pj >= A.cols) continue;
+        // next data step, four lanes per pixel
+        const int sub = threadIdx.x % kLanesPerPixel, pl = threadIdx.x / kLanesPerPixel;
+        const int ti = pl / kTile, tj = pl % kTile;
+        const int pi = i0 + ti, pj = j0 + tj;
+        if (pi < A.rows && pj < A.cols) {
             const int pix = pi * A.cols + pj;
             float tk[K], ak[K];
             bool on[K], any = false;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                tk[k] = s_ot[pl * K + k];
+                tk[k] = s_td[((ti + R) * E1 + (tj + R)) * K + k];
                 ak[k] = s_oa[pl * K + k];
                 on[k] = s_oo[pl * K + k] != 0;
                 any |= on[k];
@@ -712,17 +756,6 @@ __global__ __launch_bounds__(kTile * kTile) void iteration_kernel(
                     a_out[q] = ak[k];
                     act_out[q] = on[k] ? 1 : 0;
                 }
-            }
-        }
-    } else {
-        if (i < A.rows && j < A.cols) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int64_t q = ((int64_t)i * A.cols + j) * K + k;
-                const int o = threadIdx.x * K + k;
-                t_out[q] = s_ot[o];
-                a_out[q] = s_oa[o];
-                act_out[q] = s_oo[o];
             }
         }
     }
@@ -800,13 +833,6 @@ static IterArgs make_args(const srt3d_params& p) {
     A.Rb = p.Rb;
     A.lambda_z = p.lambda_z;
     A.r_min = p.r_min;
-    const int W = 2 * p.R + 1;
-    for (int i = 0; i < kMaxW; ++i) A.wgt[i] = 0.f;
-    for (int di = -p.R; di <= p.R; ++di)
-        for (int dj = -p.R; dj <= p.R; ++dj) {
-            const double r = 1.0 - (double)(di * di + dj * dj) / (double)((p.R + 1) * (p.R + 1));
-            A.wgt[(di + p.R) * W + (dj + p.R)] = (float)(r * r * r * r);
-        }
     return A;
 }
 
@@ -895,12 +921,12 @@ hipError_t launch_iteration(const srt3d_params& p, const float* z, const int32_t
     const IterArgs A = make_args(p);
     if (ds_next) {
         SRT3D_BY_KR(p.K_max, p.R, hipLaunchKernelGGL((iteration_kernel<KK, RR, true>), tile_grid(p),
-                                                     dim3(kTile * kTile), 0, s, A, z, n, st.hhat, st.scal, st.t[src],
+                                                     dim3(kIterThreads), 0, s, A, z, n, st.hhat, st.scal, st.t[src],
                                                      st.alpha[src], st.active[src], st.t[dst], st.alpha[dst],
                                                      st.active[dst]));
     } else {
         SRT3D_BY_KR(p.K_max, p.R, hipLaunchKernelGGL((iteration_kernel<KK, RR, false>), tile_grid(p),
-                                                     dim3(kTile * kTile), 0, s, A, z, n, st.hhat, st.scal, st.t[src],
+                                                     dim3(kIterThreads), 0, s, A, z, n, st.hhat, st.scal, st.t[src],
                                                      st.alpha[src], st.active[src], st.t[dst], st.alpha[dst],
                                                      st.active[dst]));
     }
