@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="throughput")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=96, help="serving workload: number of requests")
+    ap.add_argument("--budget-gib", type=float, default=4.0, help="serving workload: HBM budget")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     return ap.parse_args()
@@ -97,8 +99,115 @@ def cpu_baseline(frame, z_gpu, n_gpu, w, params):
     }
 
 
+def precision_report(args):
+    """Histogram sketch (256x256 x T=1024 uint16, ~4000 photons/pixel, m=16) in the three
+    arithmetic forms next to the photon sketch of the same frame; errors against the FP64
+    oracle per harmonic on sampled pixels, times by HIP events."""
+    import numpy as np
+    import torch
+
+    import paper_2203_00952_amd as srt
+    import synth
+    from oracle import sketch as OS
+
+    dev = torch.device("cuda:0")
+    w = synth.preset("precision")
+    spec = w.frame
+    frame = synth.make_frame(spec, device=dev)
+    H = synth.histogram(frame.stamps, frame.offsets, spec.T)
+    P, T, m = spec.P, spec.T, w.m
+    rng = np.random.default_rng(0)
+    sel = np.sort(rng.choice(P, 2048, replace=False))
+    zr, nr = OS.sketch_hist(synth.frames.hist_as_uint(H[torch.from_numpy(sel).to(dev)]), m)
+    floor = 1.0 / np.sqrt(np.maximum(nr, 1))[:, None]
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+        for i in range(args.steps):
+            ev[2 * i].record(stream)
+            out = fn()
+            ev[2 * i + 1].record(stream)
+        torch.cuda.synchronize()
+        return out, float(np.mean([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(args.steps)]))
+
+    forms = {}
+    table = srt.phase_table(T, dev)
+    (zp, _), t_ph = timed(lambda: srt.sketch(frame.stamps, frame.offsets, T, m, table=table))
+    zpc = zp.cpu().numpy().astype(np.float64)
+    zpc = zpc[..., 0] + 1j * zpc[..., 1]
+    for prec in ("fp32", "fp16x2", "bf16x3"):
+        ws = srt.hist_workspace(T, m, prec, dev)
+        (z, _), t_ms = timed(lambda: srt.sketch_from_hist(H, m, prec, workspace=ws))
+        zc = z.cpu().numpy().astype(np.float64)
+        zc = zc[..., 0] + 1j * zc[..., 1]
+        rel = np.abs(zc[sel] - zr) / np.maximum(np.abs(zr), floor)
+        hbytes = 2.0 * P * T + 8.0 * m * P + 4.0 * P
+        forms[prec] = {"ms": t_ms, "GB_per_s": hbytes / (t_ms * 1e-3) / 1e9,
+                       "hbm_frac": hbytes / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "max_rel_err_vs_oracle_per_harmonic": [float(v) for v in rel.max(0)],
+                       "p99_rel_err_vs_oracle": float(np.percentile(rel, 99)),
+                       "max_rel_diff_vs_photon_path": float(np.max(np.abs(zc - zpc) / np.maximum(
+                           np.abs(zpc), 1.0 / np.sqrt(np.maximum(frame.n.cpu().numpy(), 1))[:, None])))}
+    rel = np.abs(zpc[sel] - zr) / np.maximum(np.abs(zr), floor)
+    forms["photon_fp32"] = {"ms": t_ph, "max_rel_err_vs_oracle_per_harmonic": [float(v) for v in rel.max(0)]}
+    print(json.dumps({"workload": w.name, "pixels": P, "T": T, "m": m, "photons": int(frame.stamps.numel()),
+                      "error_rule": "|dz| / max(|z_ref|, n^-1/2), 2048 sampled pixels", "forms": forms}),
+          flush=True)
+
+
+def serving_report(args):
+    """Continuous batching of a Poisson stream of frames (32^2..512^2, 10..2000 photons/px,
+    T = 2048, m = 8..32, sketch + 20 iterations each).  The single-slot sequential capacity is
+    measured first; the stream is then replayed at 0.5x and 0.9x that rate on 4 slots under an
+    HBM budget.  Latency = completion - arrival."""
+    import numpy as np
+    import torch
+
+    import paper_2203_00952_amd as srt
+    import synth
+    from paper_2203_00952_amd.serve import Request, percentile, serve
+
+    dev = torch.device("cuda:0")
+    stream = synth.request_stream(seed=4, count=args.requests, rate_hz=1.0, iters=20)
+    reqs, photons = [], 0
+    for q in stream:
+        f = synth.make_frame(q.frame, device=dev)
+        params = srt.Params.default(q.frame.rows, q.frame.cols, q.frame.T, q.m, 1, iters=q.iters)
+        reqs.append(Request(q.rid, f.stamps, f.offsets, torch.from_numpy(f.irf).to(dev), f.irf_origin, params))
+        photons += int(f.stamps.numel())
+    torch.cuda.synchronize()
+    budget = int(args.budget_gib * (1 << 30))
+    serve(reqs[:4], slots=1, budget_bytes=budget)                       # warm-up
+    for r in reqs:
+        r.arrival = 0.0
+    recs, _, _ = serve(reqs, slots=1, budget_bytes=budget)
+    capacity = len(reqs) / max(r.finished for r in recs)
+    res = {"workload": "serving", "requests": len(reqs), "photons": photons, "slots": 4,
+           "hbm_budget_bytes": budget, "single_slot_capacity_frames_per_s": capacity}
+    for load in (0.5, 0.9):
+        rate = load * capacity
+        for r, q in zip(reqs, stream):
+            r.arrival = q.arrival_s / rate
+        recs, _, peak = serve(reqs, slots=4, budget_bytes=budget)
+        lat = [1e3 * r.latency for r in recs]
+        makespan = max(r.finished for r in recs)
+        res[f"load_{load}"] = {"arrival_rate_per_s": rate, "p50_ms": percentile(lat, 50),
+                               "p99_ms": percentile(lat, 99), "mean_ms": float(np.mean(lat)),
+                               "frames_per_s": len(reqs) / makespan, "peak_admitted_bytes": peak}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "precision":
+        precision_report(args)
+        return
+    if args.workload == "serving":
+        serving_report(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
                                    "part of this build (pixels shard with no communication)"}))

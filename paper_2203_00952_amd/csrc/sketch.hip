@@ -80,6 +80,50 @@ __device__ __forceinline__ void reduce_scatter(float* v, int lane, int& base) {
 // per pair), the second is that entry times exp(i w_1 x), the table entry at k = x, so each
 // photon costs MC/2 table reads (LDS bandwidth, with its data-dependent bank conflicts, is the
 // binding resource) and two extra multiply-adds per pair.
+// Add photon x's harmonics l0+1 .. l0+MC into v.
+template <int MC, bool POW2>
+__device__ __forceinline__ void add_photon(float* v, int32_t x, int l0, int T, uint32_t T8, const char* tab) {
+    const uint32_t x8 = (uint32_t)x << 3;
+    if constexpr (MC == 1) {
+        uint32_t k8 = x8;
+        if (l0 != 0) {
+            const uint32_t lx = (uint32_t)(l0 + 1) * (uint32_t)x;
+            k8 = (POW2 ? (lx & (uint32_t)(T - 1)) : (lx % (uint32_t)T)) << 3;
+        }
+        const float2 c = *reinterpret_cast<const float2*>(tab + k8);
+        v[0] += c.x;
+        v[1] += c.y;
+    } else {
+        const float2 u1 = *reinterpret_cast<const float2*>(tab + x8);   // exp(i w_1 x)
+        const uint32_t x8x2 = phase_advance<POW2>(x8, x8, T8);            // 2x mod T
+        uint32_t k8 = x8;                                                  // phase of l0 + 1
+        if (l0 != 0) {
+            const uint32_t lx = (uint32_t)(l0 + 1) * (uint32_t)x;
+            k8 = (POW2 ? (lx & (uint32_t)(T - 1)) : (lx % (uint32_t)T)) << 3;
+        }
+#pragma unroll
+        for (int j = 0; j < MC; j += 2) {
+            const float2 c = (j == 0 && l0 == 0) ? u1 : *reinterpret_cast<const float2*>(tab + k8);
+            v[2 * j] += c.x;
+            v[2 * j + 1] += c.y;
+            // next harmonic: += c * u1, as four fused multiply-adds
+            v[2 * j + 2] = fmaf(c.x, u1.x, v[2 * j + 2]);
+            v[2 * j + 2] = fmaf(-c.y, u1.y, v[2 * j + 2]);
+            v[2 * j + 3] = fmaf(c.x, u1.y, v[2 * j + 3]);
+            v[2 * j + 3] = fmaf(c.y, u1.x, v[2 * j + 3]);
+            k8 = phase_advance<POW2>(k8, x8x2, T8);
+        }
+    }
+}
+
+// One pass over a pixel's photons for harmonics l0+1 .. l0+MC.  Harmonics come in pairs: the
+// first of each pair is read from the table at its exact phase k = (l x) mod T (advanced by 2x
+// per pair), the second is that entry times exp(i w_1 x), the table entry at k = x, so each
+// photon costs MC/2 table reads (LDS bandwidth, with its data-dependent bank conflicts, is a
+// binding resource) and two extra multiply-adds per pair.  Stamps are loaded kU per lane at a
+// time, the next group while the current one is summed, to keep loads in flight.
+constexpr int kU = 4;
+
 template <int MC, int G, bool POW2>
 __device__ __forceinline__ void sketch_pass(const int32_t* __restrict__ stamps, int64_t b, int64_t e, int lane,
                                             int l0, int T, uint32_t T8, const float2* s_table, int64_t count,
@@ -91,43 +135,28 @@ __device__ __forceinline__ void sketch_pass(const int32_t* __restrict__ stamps, 
 #pragma unroll
     for (int i = 0; i < V; ++i) v[i] = 0.f;
     const int sub = lane & (G - 1);
-    for (int64_t p = b + sub; p < e; p += G) {
-        int32_t x = stamps[p];
-        if ((uint32_t)x >= (uint32_t)T) {
-            x = fold_stamp(x, T);
-            if (l0 == 0) ++bad;
-        }
-        const uint32_t x8 = (uint32_t)x << 3;
-        if constexpr (MC == 1) {
-            uint32_t k8 = x8;
-            if (l0 != 0) {
-                const uint32_t lx = (uint32_t)(l0 + 1) * (uint32_t)x;
-                k8 = (POW2 ? (lx & (uint32_t)(T - 1)) : (lx % (uint32_t)T)) << 3;
-            }
-            const float2 c = *reinterpret_cast<const float2*>(tab + k8);
-            v[0] += c.x;
-            v[1] += c.y;
-        } else {
-            const float2 u1 = *reinterpret_cast<const float2*>(tab + x8);   // exp(i w_1 x)
-            const uint32_t x8x2 = phase_advance<POW2>(x8, x8, T8);            // 2x mod T
-            uint32_t k8 = x8;                                                  // phase of l0 + 1
-            if (l0 != 0) {
-                const uint32_t lx = (uint32_t)(l0 + 1) * (uint32_t)x;
-                k8 = (POW2 ? (lx & (uint32_t)(T - 1)) : (lx % (uint32_t)T)) << 3;
-            }
+    int32_t cur[kU], nxt[kU];
+    int64_t p = b + sub;
 #pragma unroll
-            for (int j = 0; j < MC; j += 2) {
-                const float2 c = (j == 0 && l0 == 0) ? u1 : *reinterpret_cast<const float2*>(tab + k8);
-                v[2 * j] += c.x;
-                v[2 * j + 1] += c.y;
-                // next harmonic: += c * u1, as four fused multiply-adds
-                v[2 * j + 2] = fmaf(c.x, u1.x, v[2 * j + 2]);
-                v[2 * j + 2] = fmaf(-c.y, u1.y, v[2 * j + 2]);
-                v[2 * j + 3] = fmaf(c.x, u1.y, v[2 * j + 3]);
-                v[2 * j + 3] = fmaf(c.y, u1.x, v[2 * j + 3]);
-                k8 = phase_advance<POW2>(k8, x8x2, T8);
+    for (int u = 0; u < kU; ++u) cur[u] = (p + u * G < e) ? stamps[p + u * G] : 0;
+    while (p < e) {
+        const int64_t pn = p + kU * G;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) nxt[u] = (pn + u * G < e) ? stamps[pn + u * G] : 0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (p + u * G < e) {
+                int32_t x = cur[u];
+                if ((uint32_t)x >= (uint32_t)T) {
+                    x = fold_stamp(x, T);
+                    if (l0 == 0) ++bad;
+                }
+                add_photon<MC, POW2>(v, x, l0, T, T8, tab);
             }
         }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
+        p = pn;
     }
     int base = 0;
     reduce_scatter<V, G / 2>(v, lane, base);
@@ -149,12 +178,16 @@ __device__ __forceinline__ void sketch_pass(const int32_t* __restrict__ stamps, 
     }
 }
 
-template <int G, bool POW2>
+// TB is the LDS capacity of the table (a power of two >= T): a static array whose LDS offset is
+// known at compile time, so the byte phase k8 is the ds_read address with no base add.
+// MCMAX bounds the harmonics per pass (16 or 32): the register budget, and with it occupancy,
+// follows the largest pass the kernel contains, so m <= 16 uses a kernel without the 32 pass.
+template <int G, bool POW2, int TB, int MCMAX>
 __global__ __launch_bounds__(256) void sketch_photons_kernel(
     const int32_t* __restrict__ stamps, int64_t N, const int64_t* __restrict__ offsets, int P, int T, int m,
     const float2* __restrict__ table, float* __restrict__ z, int32_t* __restrict__ nout,
     double* __restrict__ acc, int64_t* __restrict__ nacc, int32_t* __restrict__ err) {
-    extern __shared__ float2 s_table[];
+    __shared__ float2 s_table[TB];
     for (int i = threadIdx.x; i < T; i += blockDim.x) s_table[i] = table[i];
     __syncthreads();
 
@@ -184,9 +217,12 @@ __global__ __launch_bounds__(256) void sketch_photons_kernel(
         }
         for (int l0 = 0; l0 < m;) {
             const int rem = m - l0;
-            const int mc = rem >= 32 ? 32 : (1 << (31 - __builtin_clz((unsigned)rem)));
+            const int mc = rem >= MCMAX ? MCMAX : (1 << (31 - __builtin_clz((unsigned)rem)));
             switch (mc) {
-                case 32: sketch_pass<32, G, POW2>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps); break;
+                case 32:
+                    if constexpr (MCMAX >= 32)
+                        sketch_pass<32, G, POW2>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps);
+                    break;
                 case 16: sketch_pass<16, G, POW2>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps); break;
                 case 8: sketch_pass<8, G, POW2>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps); break;
                 case 4: sketch_pass<4, G, POW2>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps); break;
@@ -206,27 +242,40 @@ __global__ __launch_bounds__(256) void sketch_photons_kernel(
     }
 }
 
-template <int G, bool POW2>
+template <int G, bool POW2, int TB, int MCMAX>
 static hipError_t launch_sketch_g(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T, int m,
                                   const float2* table, float* z, int32_t* n, double* acc, int64_t* nacc,
                                   int32_t* err, hipStream_t s) {
     const int threads = 256;
-    const size_t lds = (size_t)T * sizeof(float2);
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t st = hipGetDevice(&dev);
     if (st != hipSuccess) return st;
     st = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (st != hipSuccess) return st;
-    st = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sketch_photons_kernel<G, POW2>, threads, lds);
+    st = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sketch_photons_kernel<G, POW2, TB, MCMAX>, threads, 0);
     if (st != hipSuccess) return st;
     if (per_cu < 1) per_cu = 1;
     const int64_t groups_per_block = threads / G;
     const int64_t need = ((int64_t)P + groups_per_block - 1) / groups_per_block;
     const int64_t cap = (int64_t)cus * per_cu;
     const unsigned blocks = (unsigned)(need < cap ? need : cap);
-    hipLaunchKernelGGL((sketch_photons_kernel<G, POW2>), dim3(blocks), dim3(threads), lds, s, stamps, N, offsets,
+    hipLaunchKernelGGL((sketch_photons_kernel<G, POW2, TB, MCMAX>), dim3(blocks), dim3(threads), 0, s, stamps, N, offsets,
                        P, T, m, table, z, n, acc, nacc, err);
     return hipGetLastError();
+}
+
+template <int G, bool POW2>
+static hipError_t launch_sketch_tb(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T, int m,
+                                   const float2* table, float* z, int32_t* n, double* acc, int64_t* nacc,
+                                   int32_t* err, hipStream_t s) {
+#define SRT3D_TB(TBV)                                                                                            \
+    return m <= 16 ? launch_sketch_g<G, POW2, TBV, 16>(stamps, N, offsets, P, T, m, table, z, n, acc, nacc, err, s) \
+                   : launch_sketch_g<G, POW2, TBV, 32>(stamps, N, offsets, P, T, m, table, z, n, acc, nacc, err, s)
+    if (T <= 1024) SRT3D_TB(1024);
+    if (T <= 2048) SRT3D_TB(2048);
+    if (T <= 4096) SRT3D_TB(4096);
+    SRT3D_TB(8192);
+#undef SRT3D_TB
 }
 
 // Lanes per pixel from the mean photon count: enough lanes to keep the stride loop busy, few
@@ -247,8 +296,8 @@ hipError_t launch_sketch_photons(const int32_t* stamps, int64_t N, const int64_t
     const char* env = getenv("SRT3D_SKETCH_LANES");
     const int G = env ? atoi(env) : lanes_per_pixel(N, P);
 #define SRT3D_SK(GG)                                                                                              \
-    return pow2 ? launch_sketch_g<GG, true>(stamps, N, offsets, P, T, m, table, z, n, acc, nacc, err, s)          \
-                : launch_sketch_g<GG, false>(stamps, N, offsets, P, T, m, table, z, n, acc, nacc, err, s)
+    return pow2 ? launch_sketch_tb<GG, true>(stamps, N, offsets, P, T, m, table, z, n, acc, nacc, err, s)         \
+                : launch_sketch_tb<GG, false>(stamps, N, offsets, P, T, m, table, z, n, acc, nacc, err, s)
     switch (G) {
         case 4: SRT3D_SK(4);
         case 8: SRT3D_SK(8);
