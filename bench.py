@@ -72,7 +72,7 @@ def cpu_baseline(frame, z_gpu, n_gpu, w, params):
     S = 2048
     sel = np.sort(rng.choice(spec.P, S, replace=False))
     it_sample = 5
-    op = O.Params(spec.T, w.m, w.K_max, iters=params.iters)
+    op = O.Params(spec.T, w.m, w.K_max, iters=params.iters, r_min=params.r_min)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         OS.sketch(st_np, off_np, spec.T, w.m, pixels=sel)
@@ -226,7 +226,7 @@ def main():
     frame = synth.make_frame(spec, device=dev)
     N = frame.stamps.numel()
     P, T, m = spec.P, spec.T, w.m
-    params = srt.Params.default(spec.rows, spec.cols, T, m, w.K_max, iters=w.iters)
+    params = srt.Params.default(spec.rows, spec.cols, T, m, w.K_max, iters=w.iters, r_min=w.r_min)
     irf = torch.from_numpy(frame.irf).to(dev)
     table = srt.phase_table(T, dev)
     z = torch.empty((P, m, 2), dtype=torch.float32, device=dev)

@@ -18,6 +18,7 @@ class Workload:
     K_max: int
     iters: int
     description: str
+    r_min: float = 1.0          # photons below which a reconstructed point is removed
 
     def with_seed(self, seed: int) -> "Workload":
         return replace(self, frame=replace(self.frame, seed=seed))
@@ -41,7 +42,8 @@ PRESETS = {
         iters=0, description="256x256 uint16 histograms, T=1024, ~4000 photons/px, m=16"),
     "billion": Workload(
         "billion", FrameSpec(512, 512, 8192, 8.0, 4000.0, 0.5, 3, seed=5), m=32, K_max=3,
-        iters=50, description="512x512 px, T=8192, <=3 surfaces/px, ~4000 photons/px, SBR=0.5, m=32"),
+        iters=50, description="512x512 px, T=8192, <=3 surfaces/px, ~4000 photons/px, SBR=0.5, m=32",
+        r_min=100.0),
 }
 
 
