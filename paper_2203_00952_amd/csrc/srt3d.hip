@@ -4,9 +4,9 @@
 //   frame_constants   hhat_l = sum_i h_i exp(i w_l (i - o)) / sum h (eq. 4) in FP64, the sums
 //                     sum |hhat|^2 and sum w^2 |hhat|^2, the impulse-response spread and the
 //                     depth gate; one workgroup, one wave per harmonic subset
-//   init              greedy sketched matched filter on the grid tau = 0, s, 2s, ...: one wave per
-//                     pixel, lanes over grid points, harmonics by a phasor recurrence re-anchored
-//                     every 16 harmonics at the exact integer phase (l tau) mod T; also the
+//   init              greedy sketched matched filter on the grid tau = 0, s, 2s, ...: the filter
+//                     over all pixels and grid points is a real matrix product on the FP32 matrix
+//                     cores (16 pixels per wave) with the argmax in its epilogue; also the
 //                     per-workgroup maximum photon count
 //   step_sizes        frame maximum photon count and the two step sizes
 //   data_step         per pixel: residual e = Phi - z, depth step, residual at the new depths,
@@ -191,98 +191,184 @@ __global__ __launch_bounds__(256) void frame_constants_kernel(const double* __re
 }
 
 // ----------------------------------------------------------------------------- init
-// One wave per pixel.  c(tau_g) = Re sum_l conj(hhat_l) w_l exp(-i w_l tau_g) for the lane's grid
-// points; y_l = conj(hhat_l) w_l is held by lane l - 1 and broadcast with readlane.
-template <int K>
+// c(tau_g) = Re sum_l conj(hhat_l) w_l exp(-i w_l tau_g) over all pixels and grid points is the
+// real product C = Y E: Y[p][k] holds the real (k even) and imaginary (k odd) parts of
+// conj(hhat_l) w_l for k = 2(l-1) + {0, 1}, and E[k][g] = cos / sin(w_l tau_g) at the exact phase
+// (l tau_g) mod T.  One wave takes 16 pixels: its Y rows stay in registers as the A operand of
+// v_mfma_f32_16x16x4_f32, E is read as prebuilt B-operand fragments, and the argmax of every row
+// is folded into the epilogue of each 16-column tile (larger c, then smaller tau).  Each greedy
+// pick subtracts its atom from the working sketch w and the product is redone.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// EB[(nt * KS + ks) * 64 + lane] = E[4 ks + lane / 16][16 nt + lane % 16], zero outside 2m x G.
+__global__ void init_grid_table_kernel(int T, int m, int stride, int G, int KS, int NT, float* __restrict__ EB) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= NT * KS * 64) return;
+    const int lane = idx & 63, ks = (idx >> 6) % KS, nt = (idx >> 6) / KS;
+    const int k = 4 * ks + (lane >> 4), g = 16 * nt + (lane & 15);
+    double v = 0.0;
+    if (k < 2 * m && g < G) {
+        const int64_t ph = ((int64_t)(k / 2 + 1) * ((int64_t)g * stride)) % T;
+        double sn, cs;
+        sincospi(2.0 * (double)ph / (double)T, &sn, &cs);
+        v = (k & 1) ? sn : cs;
+    }
+    EB[idx] = (float)v;
+}
+
+template <int K, int KSMAX>
 __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, const int32_t* __restrict__ n,
                                                    const float* __restrict__ hhat, const float* __restrict__ scal,
-                                                   int P, int T, int m, int stride, float r_min,
-                                                   float* __restrict__ t_out, float* __restrict__ a_out,
-                                                   uint8_t* __restrict__ act_out, int* __restrict__ nmax_part) {
+                                                   const float* __restrict__ EB, int P, int T, int m, int stride,
+                                                   int G, int KS, int NT, float r_min, float* __restrict__ t_out,
+                                                   float* __restrict__ a_out, uint8_t* __restrict__ act_out,
+                                                   int* __restrict__ nmax_part) {
     __shared__ int s_nmax[4];
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int G = (T + stride - 1) / stride;
-    const float e2 = scal[4];
-    const float invT = 1.0f / (float)T, twoinvT = 2.0f / (float)T;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = lane & 15, kq = lane >> 4;          // A row (pixel) / k quarter of this lane
+    const float e2 = scal[4], invT = 1.0f / (float)T, twoinvT = 2.0f / (float)T;
+    const int groups = (P + 15) / 16;
     const int waves_total = gridDim.x * (blockDim.x >> 6);
+    const int l_first = kq / 2 + 1;                    // harmonic of ks = 0; +2 per ks
+    float2 hl[KSMAX];
+#pragma unroll
+    for (int ks = 0; ks < KSMAX; ++ks) {
+        const int k = 4 * ks + kq;
+        hl[ks] = (ks < KS && k < 2 * m) ? reinterpret_cast<const float2*>(hhat)[k / 2] : make_float2(0.f, 0.f);
+    }
     int nmax = 0;
-    const float2 hl = lane < m ? reinterpret_cast<const float2*>(hhat)[lane] : make_float2(0.f, 0.f);
-
-    for (int pix = blockIdx.x * (blockDim.x >> 6) + wv; pix < P; pix += waves_total) {
-        float2 wl = lane < m ? reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m)[lane] : make_float2(0.f, 0.f);
-        const int np = n[pix];
+    for (int grp = blockIdx.x * (blockDim.x >> 6) + wv; grp < groups; grp += waves_total) {
+        const int prow = grp * 16 + r;
+        const bool rv = prow < P;
+        float2 w[KSMAX];
+#pragma unroll
+        for (int ks = 0; ks < KSMAX; ++ks) {
+            const int k = 4 * ks + kq;
+            w[ks] = (rv && ks < KS && k < 2 * m) ? reinterpret_cast<const float2*>(z + (int64_t)prow * 2 * m)[k / 2]
+                                                  : make_float2(0.f, 0.f);
+        }
+        const int np = rv ? n[prow] : 0;
         nmax = max(nmax, np);
-        int tau[K];
-        float amp[K];
+        int tau_row[K][4];                              // picks of C rows 4 kq + i
+        int tau_mine[K];                                // picks of A row r
+        float amp_mine[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const float yx = hl.x * wl.x + hl.y * wl.y;    // conj(hhat) * w
-            const float yy = hl.x * wl.y - hl.y * wl.x;
-            float best = -INFINITY;
-            int bestg = 0x7fffffff;
-            // wave-uniform loops (every lane active): readlane reads lanes that hold y
-            for (int g0 = 0; g0 < G; g0 += 64) {
-                const int g = g0 + lane;
-                const int tg = (g < G ? g : 0) * stride;
-                bool skip = g >= G;
+            float ya[KSMAX];
 #pragma unroll
-                for (int j = 0; j < k; ++j) {
-                    int d = tg - tau[j];
-                    d = d < 0 ? -d : d;
-                    d = min(d, T - d);
-                    skip |= (int64_t)d * m < (int64_t)T;
-                }
-                float2 u1 = make_float2(1.f, 0.f), u = u1;
-                float c = 0.f;
-                for (int l = 0; l < m; ++l) {
-                    if ((l & 15) == 0) {           // exact anchor: phase ((l+1) tau) mod T
-                        u = phasor_int(mod_small((l + 1) * tg, T, invT), twoinvT);
-                        if (l == 0) u1 = u;
-                    } else {
-                        u = cmul(u, u1);
+            for (int ks = 0; ks < KSMAX; ++ks) {        // conj(hhat) w, real part for even k
+                const float re = hl[ks].x * w[ks].x + hl[ks].y * w[ks].y;
+                const float im = hl[ks].x * w[ks].y - hl[ks].y * w[ks].x;
+                ya[ks] = (kq & 1) ? im : re;
+            }
+            float best[4];
+            int bestg[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                best[i] = -INFINITY;
+                bestg[i] = 0x7fffffff;
+            }
+            // two column tiles per pass: two independent accumulation chains
+            auto scan = [&](const v4f& acc, int nt) {
+                const int g = 16 * nt + r;              // column of this lane's C entries
+                const int tg = g * stride;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    bool excl = g >= G;
+#pragma unroll
+                    for (int j = 0; j < k; ++j) {
+                        int d = tg - tau_row[j][i];
+                        d = d < 0 ? -d : d;
+                        d = min(d, T - d);
+                        excl |= (int64_t)d * m < (int64_t)T;
                     }
-                    const float ax = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yx), l));
-                    const float ay = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yy), l));
-                    c += ax * u.x + ay * u.y;      // Re(y_l exp(-i w_l tau))
+                    if (!excl && acc[i] > best[i]) {     // g grows with nt: ties keep the smaller
+                        best[i] = acc[i];
+                        bestg[i] = g;
+                    }
                 }
-                if (!skip && c > best) {           // g increases per lane: ties keep the smaller g
-                    best = c;
-                    bestg = g;
+            };
+            for (int nt = 0; nt < NT; nt += 2) {
+                const float* eb0 = EB + (int64_t)nt * KS * 64 + lane;
+                v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+                if (nt + 1 < NT) {
+                    const float* eb1 = eb0 + KS * 64;
+#pragma unroll
+                    for (int ks = 0; ks < KSMAX; ++ks)
+                        if (ks < KS) {
+                            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[ks], eb0[ks * 64], acc0, 0, 0, 0);
+                            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[ks], eb1[ks * 64], acc1, 0, 0, 0);
+                        }
+                    scan(acc0, nt);
+                    scan(acc1, nt + 1);
+                } else {
+#pragma unroll
+                    for (int ks = 0; ks < KSMAX; ++ks)
+                        if (ks < KS) acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[ks], eb0[ks * 64], acc0, 0, 0, 0);
+                    scan(acc0, nt);
                 }
             }
-            for (int o = 32; o > 0; o >>= 1) {     // wave argmax: larger c, then smaller g
-                const float ob = __shfl_xor(best, o, 64);
-                const int og = __shfl_xor(bestg, o, 64);
-                if (ob > best || (ob == best && og < bestg)) {
-                    best = ob;
-                    bestg = og;
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float ob = __shfl_xor(best[i], o, 64);
+                    const int og = __shfl_xor(bestg[i], o, 64);
+                    if (ob > best[i] || (ob == best[i] && og < bestg[i])) {
+                        best[i] = ob;
+                        bestg[i] = og;
+                    }
                 }
             }
-            const float a = (bestg == 0x7fffffff) ? 0.f : fmaxf(0.f, best / e2);
-            const int tk = (bestg == 0x7fffffff) ? 0 : bestg * stride;
-            tau[k] = tk;
-            amp[k] = a;
-            if (lane < m) {                        // w_l -= a hhat_l exp(i w_l tau)
-                const float2 g = cmul(hl, phasor_int(mod_small((lane + 1) * tk, T, invT), twoinvT));
-                wl.x -= a * g.x;
-                wl.y -= a * g.y;
+            float arow[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bool none = bestg[i] == 0x7fffffff;
+                arow[i] = none ? 0.f : fmaxf(0.f, best[i] / e2);
+                tau_row[k][i] = none ? 0 : bestg[i] * stride;
+            }
+            // this lane's A row r: its pick sits in lanes 16 (r / 4) .. + 15, element r % 4
+            const int src = (r >> 2) * 16;
+            float a_sel = 0.f;
+            int t_sel = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float av = __shfl(arow[i], src, 64);
+                const int tv = __shfl(tau_row[k][i], src, 64);
+                if ((r & 3) == i) {
+                    a_sel = av;
+                    t_sel = tv;
+                }
+            }
+            amp_mine[k] = a_sel;
+            tau_mine[k] = t_sel;
+            if (k + 1 < K) {                            // w_l -= a hhat_l exp(i w_l tau)
+                float2 u = phasor_int(mod_small(l_first * t_sel, T, invT), twoinvT);
+                const float2 step = phasor_int(mod_small(2 * t_sel, T, invT), twoinvT);
+#pragma unroll
+                for (int ks = 0; ks < KSMAX; ++ks) {
+                    const float2 gv = cmul(hl[ks], u);
+                    w[ks].x -= a_sel * gv.x;
+                    w[ks].y -= a_sel * gv.y;
+                    u = cmul(u, step);
+                }
             }
         }
-        if (lane == 0) {
+        if (kq == 0 && rv) {
             bool all[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) all[k] = true;
-            project_capped_simplex<K>(amp, all);
+            project_capped_simplex<K>(amp_mine, all);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const bool on = np > 0 && (float)np * amp[k] >= r_min;
-                t_out[(int64_t)pix * K + k] = (float)tau[k];
-                a_out[(int64_t)pix * K + k] = on ? amp[k] : 0.f;
-                act_out[(int64_t)pix * K + k] = on ? 1 : 0;
+                const bool on = np > 0 && (float)np * amp_mine[k] >= r_min;
+                t_out[(int64_t)prow * K + k] = (float)tau_mine[k];
+                a_out[(int64_t)prow * K + k] = on ? amp_mine[k] : 0.f;
+                act_out[(int64_t)prow * K + k] = on ? 1 : 0;
             }
         }
     }
+    for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
     if (lane == 0) s_nmax[wv] = nmax;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -841,7 +927,23 @@ static inline dim3 tile_grid(const srt3d_params& p) {
     return dim3((unsigned)((p.cols + kTile - 1) / kTile), (unsigned)((p.rows + kTile - 1) / kTile));
 }
 
-size_t init_ws_bytes(const srt3d_params&) { return (size_t)kInitBlocksMax * sizeof(int); }
+struct InitGrid {
+    int stride, G, KS, NT;
+};
+static InitGrid init_grid(const srt3d_params& p) {
+    InitGrid g;
+    g.stride = p.init_stride > 0 ? p.init_stride : (p.T / (8 * p.m) > 1 ? p.T / (8 * p.m) : 1);
+    g.G = (p.T + g.stride - 1) / g.stride;
+    g.KS = (2 * p.m + 3) / 4;
+    g.NT = (g.G + 15) / 16;
+    return g;
+}
+
+// workspace: per-workgroup photon-count maxima, then the grid table (B-operand fragments)
+size_t init_ws_bytes(const srt3d_params& p) {
+    const InitGrid g = init_grid(p);
+    return (size_t)kInitBlocksMax * sizeof(int) + (size_t)g.NT * g.KS * 64 * sizeof(float);
+}
 
 #define SRT3D_BY_K(K_, CALL)                            \
     switch (K_) {                                       \
@@ -873,17 +975,28 @@ hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int 
                        p.tau_z, st.hhat, st.scal);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int stride = p.init_stride > 0 ? p.init_stride : (p.T / (8 * p.m) > 1 ? p.T / (8 * p.m) : 1);
+    const InitGrid g = init_grid(p);
+    int* part = reinterpret_cast<int*>(ws);
+    float* EB = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + (size_t)kInitBlocksMax * sizeof(int));
+    const int tab = g.NT * g.KS * 64;
+    hipLaunchKernelGGL(init_grid_table_kernel, dim3((tab + 255) / 256), dim3(256), 0, s, p.T, p.m, g.stride, g.G, g.KS,
+                       g.NT, EB);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     int dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    int64_t blocks = ((int64_t)P + 3) / 4;
+    int64_t blocks = ((int64_t)(P + 15) / 16 + 3) / 4;
     const int64_t cap = std::min<int64_t>((int64_t)cus * 8, kInitBlocksMax);
     if (blocks > cap) blocks = cap;
-    int* part = reinterpret_cast<int*>(ws);
-    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((init_kernel<KK>), dim3((unsigned)blocks), dim3(256), 0, s, z, n,
-                                           st.hhat, st.scal, P, p.T, p.m, stride, p.r_min, st.t[0], st.alpha[0],
-                                           st.active[0], part));
+#define SRT3D_INIT(KSM)                                                                                           \
+    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((init_kernel<KK, KSM>), dim3((unsigned)blocks), dim3(256), 0, s, z, n, \
+                                           st.hhat, st.scal, EB, P, p.T, p.m, g.stride, g.G, g.KS, g.NT, p.r_min, \
+                                           st.t[0], st.alpha[0], st.active[0], part))
+    if (g.KS <= 4) { SRT3D_INIT(4); }
+    else if (g.KS <= 8) { SRT3D_INIT(8); }
+    else if (g.KS <= 16) { SRT3D_INIT(16); }
+    else { SRT3D_INIT(32); }
+#undef SRT3D_INIT
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(step_sizes_kernel, dim3(1), dim3(256), 0, s, part, (int)blocks, p.K_max, p.eta_t, p.eta_a,
                        st.scal);
