@@ -139,6 +139,23 @@ int srt3d_sketch(const int32_t* d_stamps, int64_t N, const int64_t* d_offsets, i
                  double* d_acc, int64_t* d_nacc, int32_t* d_err, void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Sketch of photon time stamps through each pixel's unit-bin histogram -- Section 2: the
+ * stamps are integer bins, so eq. (3) over the photons equals eq. (3) over the histogram of
+ * eq. (2).  Same arguments, outputs, long-exposure accumulators, error counters and
+ * constraints as srt3d_sketch, plus m <= 32.  One kernel launch.
+ * Each pixel's histogram is built in on-chip memory (8-bit bins; a bin that would pass 255 is
+ * detected and its pixel recomputed in chunks of at most 255 photons) and contracted with the
+ * DFT columns on the FP16 matrix cores: with x = 64 j + r, the product over r uses an exact
+ * two-term FP16 split of exp(i w_l r) and FP32 accumulation, and the sum over j multiplies
+ * by exp(i w_l 64 j) from the phase table in FP32.  The per-photon cost is one on-chip
+ * integer add, independent of m.  The result differs from srt3d_sketch by rounding only
+ * (about 2^-22 of sum |counts| in S before the division by n).
+ * ------------------------------------------------------------------------------------- */
+int srt3d_sketch_binned(const int32_t* d_stamps, int64_t N, const int64_t* d_offsets, int32_t P,
+                        int32_t T, int32_t m, const float* d_table, float* d_z, int32_t* d_n,
+                        double* d_acc, int64_t* d_nacc, int32_t* d_err, void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * Sketch of per-pixel ToA histograms -- eq. (2) with unit bins [t, t+1), then eq. (3):
  *     S_l = sum_t H[p][t] exp(i w_l t),  n = sum_t H[p][t],  z = S / n,
  * computed as the product H [P x T] . F [T x 2m] with F the cos/sin DFT columns.

@@ -45,6 +45,7 @@ _SIGS = {
     "srt3d_params_default": (None, [ctypes.POINTER(_Params), _I32, _I32, _I32, _I32, _I32]),
     "srt3d_phase_table": (_I32, [_I32, _VP, _VP]),
     "srt3d_sketch": (_I32, [_VP, _I64, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "srt3d_sketch_binned": (_I32, [_VP, _I64, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "srt3d_hist_workspace_bytes": (_SZ, [_I32, _I32, _I32]),
     "srt3d_hist_prepare": (_I32, [_I32, _I32, _I32, _VP, _SZ, _VP]),
     "srt3d_sketch_from_hist": (_I32, [_VP, _I32, _I32, _I32, _I32, _VP, _SZ, _VP, _VP, _VP]),
@@ -130,9 +131,17 @@ def cached_phase_table(T: int, device) -> torch.Tensor:
     return _TABLES[key]
 
 
+SKETCH_METHODS = ("photon", "binned")
+
+
 def sketch(stamps: torch.Tensor, offsets: torch.Tensor, T: int, m: int, *, acc=None, nacc=None, err=None,
-           z=None, n=None, table=None):
-    """Photon sketch (eq. 3).  Returns (z float32 [P, m, 2], n int32 [P])."""
+           z=None, n=None, table=None, method: str = "photon"):
+    """Photon sketch (eq. 3).  Returns (z float32 [P, m, 2], n int32 [P]).
+
+    method "photon": photon-parallel pass over the phase table (srt3d_sketch);
+    method "binned": per-pixel histogram on the FP16 matrix cores (srt3d_sketch_binned, m <= 32)."""
+    if method not in SKETCH_METHODS:
+        raise ValueError(f"sketch: unknown method {method!r}")
     P = offsets.numel() - 1
     dev = offsets.device
     ps = _dev(stamps, torch.int32, "stamps")
@@ -148,9 +157,10 @@ def sketch(stamps: torch.Tensor, offsets: torch.Tensor, T: int, m: int, *, acc=N
         if not (2 <= T and T * 8 <= 65536):
             raise ValueError("sketch: invalid T")
         table = cached_phase_table(T, dev)
-    _check(_lib().srt3d_sketch(ps, stamps.numel(), po, P, T, m, _dev(table, torch.float32, "table"),
-                               _dev(z, torch.float32, "z"), _dev(n, torch.int32, "n"), _ptr(acc), _ptr(nacc),
-                               _ptr(err), _stream(dev)), "srt3d_sketch")
+    name = "srt3d_sketch" if method == "photon" else "srt3d_sketch_binned"
+    _check(getattr(_lib(), name)(ps, stamps.numel(), po, P, T, m, _dev(table, torch.float32, "table"),
+                                 _dev(z, torch.float32, "z"), _dev(n, torch.int32, "n"), _ptr(acc), _ptr(nacc),
+                                 _ptr(err), _stream(dev)), name)
     return z, n
 
 

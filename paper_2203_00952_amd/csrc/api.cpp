@@ -72,6 +72,17 @@ int srt3d_sketch(const int32_t* d_stamps, int64_t N, const int64_t* d_offsets, i
                                             d_z, d_n, d_acc, d_nacc, d_err, as_stream(stream)));
 }
 
+int srt3d_sketch_binned(const int32_t* d_stamps, int64_t N, const int64_t* d_offsets, int32_t P, int32_t T,
+                        int32_t m, const float* d_table, float* d_z, int32_t* d_n, double* d_acc, int64_t* d_nacc,
+                        int32_t* d_err, void* stream) {
+    if (P < 1 || N < 0 || !sketch_dims_ok(T, m) || m > 32) return SRT3D_EINVAL;
+    if ((!d_stamps && N > 0) || !d_offsets || !d_table || !d_z || !d_n) return SRT3D_EINVAL;
+    if ((d_acc == nullptr) != (d_nacc == nullptr)) return SRT3D_EINVAL;
+    if (!aligned(d_table, 8) || !aligned(d_z, 8)) return SRT3D_EINVAL;
+    return dev_status(launch_sketch_binned(d_stamps, N, d_offsets, P, T, m, reinterpret_cast<const float2*>(d_table),
+                                           d_z, d_n, d_acc, d_nacc, d_err, as_stream(stream)));
+}
+
 size_t srt3d_hist_workspace_bytes(int32_t T, int32_t m, int32_t precision) {
     if (!sketch_dims_ok(T, m) || m > 32 || precision < 0 || precision > 2) return 0;
     return hist_ws_bytes(T, m, precision);

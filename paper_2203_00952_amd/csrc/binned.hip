@@ -1,0 +1,407 @@
+// Photon sketch through a per-pixel histogram on the matrix cores (Section 2, eq. 2 with unit
+// bins, then eq. 3).  Same result as the photon-parallel pass, by a different route.
+//
+// Stamps are integers in [0, T), so the sketch of the photons equals the sketch of their unit-bin
+// histogram H.  Write a stamp as x = 64 j + r (j < J = ceil(T / 64), r < 64); then
+//     S_l = sum_j W_l[j] G_l[j],   G_l[j] = sum_r H[j][r] V_l[r],
+//     V_l[r] = exp(i w_l r),       W_l[j] = exp(i w_l 64 j),
+// with both phases reduced exactly mod T and read from the FP32 phase table.  Per pixel:
+//  * H is built in LDS by integer atomics, four 8-bit bins to a 32-bit word (one ds_add per
+//    photon, no per-photon harmonic work).  A bin that passes 255 carries into its neighbour;
+//    that is detected exactly (the byte sum then falls short of n) and the pixel is redone in
+//    chunks of at most 255 photons, which cannot overflow.
+//  * G = H[J x 64] . V[64 x 2m] runs as v_mfma_f32_16x16x32_f16.  Counts <= 255 are exact in
+//    FP16; V is split as V = V1 + 2^-11 V2 with V1 = fp16(V), V2 = fp16(2^11 (V - V1)), each
+//    product accumulated in FP32 in its own tile, so G carries V to about 2^-22.
+//  * The twiddle sum over j is FP32 FMAs in the MFMA output layout, then a fixed-order sum
+//    over the lanes' row groups; z = S / n in FP64 as in the photon pass.
+// The per-photon cost is one LDS atomic; the per-pixel cost is T * 2m * 2 MFMA multiply-adds.
+//
+// Work layout: every wave owns a contiguous range of pixels (so one contiguous range of stamps)
+// and its own histogram in LDS, and works through its pixels without any workgroup barrier, so
+// the latencies of one wave's steps (loads, LDS round trips, MFMA chains) overlap the work of
+// the others.  Stamps stream in runs of U per lane; two register sets alternate so the next run
+// is always in flight, across pixel boundaries.  The twiddles W are shared by the workgroup's
+// four waves in LDS; the V fragments (B operands) stay in registers.
+#include "common.hpp"
+
+namespace srt3d {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef _Float16 v2h __attribute__((ext_vector_type(2)));
+
+constexpr int kBinThreads = 256;
+constexpr int kBinWaves = kBinThreads / kWave;
+constexpr int kRowBins = 64;            // r range: bins per histogram row
+constexpr int kSafeChunk = 255;         // photons per chunk that cannot overflow an 8-bit bin
+
+// Eight 8-bit counts (two words) as eight FP16 values b - c: each byte b becomes the FP16 bit
+// pattern 0x6400 | b, which is 1024 + b, and bias = -(1024 + c) is then added exactly.
+__device__ __forceinline__ v8h bytes_to_h8(uint32_t w0, uint32_t w1, v2h bias) {
+    const uint32_t k64 = 0x64646464u;
+    uint32_t u[4];
+    u[0] = __builtin_amdgcn_perm(k64, w0, 0x04010400u);
+    u[1] = __builtin_amdgcn_perm(k64, w0, 0x04030402u);
+    u[2] = __builtin_amdgcn_perm(k64, w1, 0x04010400u);
+    u[3] = __builtin_amdgcn_perm(k64, w1, 0x04030402u);
+    v8h out;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        v2h h = __builtin_bit_cast(v2h, u[i]);
+        h = h + bias;
+        out[2 * i] = h[0];
+        out[2 * i + 1] = h[1];
+    }
+    return out;
+}
+
+__device__ __forceinline__ _Float16 split_hi(float v) { return (_Float16)v; }
+__device__ __forceinline__ _Float16 split_lo(float v) { return (_Float16)((v - (float)(_Float16)v) * 2048.0f); }
+
+// Sum over the 64 lanes: inclusive scans within each row of 16 lanes (DPP row shifts, no LDS),
+// then the four row totals.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 15) + (uint32_t)__builtin_amdgcn_readlane((int)v, 31) +
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 47) + (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// B operands: lane c = lane & 15 is column (harmonic l = 16 q + c + 1), g = lane >> 4 its
+// k group (bins r = 32 ks + 8 g .. + 7).
+template <int Q>
+struct VFrags {
+    v8h hi[2][Q][2], lo[2][Q][2];     // [k-step][q][re/im]
+};
+
+template <int Q>
+__device__ __forceinline__ void load_vfrags(VFrags<Q>& V, const float2* __restrict__ table, int T, int m, int lane) {
+    const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int l = 16 * q + c + 1;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int r = 32 * ks + 8 * g + e;
+                float cv = 0.f, sv = 0.f;
+                if (l <= m) {
+                    const float2 t = table[(l * r) % T];
+                    cv = t.x;
+                    sv = t.y;
+                }
+                V.hi[ks][q][0][e] = split_hi(cv);
+                V.lo[ks][q][0][e] = split_lo(cv);
+                V.hi[ks][q][1][e] = split_hi(sv);
+                V.lo[ks][q][1][e] = split_lo(sv);
+            }
+        }
+    }
+}
+
+// Add the contribution of the histogram minus a constant `dc` in every bin to the lane's partial
+// sums sre/sim (harmonic 16 q + c + 1, summed over the lane's rows 16 mt + 4 g + i) and the
+// lane's raw byte sum to bsum.  s_w[j][16 Q] holds W_l[j] for l = 1 .. 16 Q.
+//
+// The constant changes nothing exactly: the sum of exp(i w_l t) over all T bins is zero for
+// 0 < l < T.  With dc near the mean count it removes the common level of the bins, which would
+// otherwise make every row sum G_l[j] of a low harmonic large (a row spans 64/T of a period)
+// and the sum over j a cancellation whose FP32 rounding grows like n instead of sqrt(n).  It
+// needs every A element to be a real bin (T a multiple of 1024, no padding rows); otherwise
+// the caller passes dc = 0.
+template <int Q>
+__device__ __forceinline__ void mfma_tiles(const uint8_t* hist, const float2* s_w, const VFrags<Q>& V, int MT,
+                                           int lane, int dc, float* sre, float* sim, uint32_t& bsum) {
+    const int c = lane & 15, g = lane >> 4;
+    const _Float16 bh = (_Float16)(float)(-1024 - dc);
+    const v2h bias = {bh, bh};
+    for (int mt = 0; mt < MT; ++mt) {
+        const uint8_t* row = hist + (16 * mt + c) * kRowBins + 8 * g;
+        const uint2 w0 = *reinterpret_cast<const uint2*>(row);
+        const uint2 w1 = *reinterpret_cast<const uint2*>(row + 32);
+        float2 wt[4][Q];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) wt[i][q] = s_w[(16 * mt + 4 * g + i) * (16 * Q) + 16 * q + c];
+        bsum = __builtin_amdgcn_sad_u8(w0.x, 0u, bsum);
+        bsum = __builtin_amdgcn_sad_u8(w0.y, 0u, bsum);
+        bsum = __builtin_amdgcn_sad_u8(w1.x, 0u, bsum);
+        bsum = __builtin_amdgcn_sad_u8(w1.y, 0u, bsum);
+        const v8h A0 = bytes_to_h8(w0.x, w0.y, bias), A1 = bytes_to_h8(w1.x, w1.y, bias);
+        v4f hi[Q][2], lo[Q][2];
+        const v4f zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                hi[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, V.hi[0][q][p], zero, 0, 0, 0);
+                lo[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, V.lo[0][q][p], zero, 0, 0, 0);
+            }
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                hi[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, V.hi[1][q][p], hi[q][p], 0, 0, 0);
+                lo[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, V.lo[1][q][p], lo[q][p], 0, 0, 0);
+            }
+        // output element i of a tile: row 4 g + i, column c
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float gr = fmaf(lo[q][0][i], 1.0f / 2048.0f, hi[q][0][i]);
+                const float gi = fmaf(lo[q][1][i], 1.0f / 2048.0f, hi[q][1][i]);
+                const float wr = wt[i][q].x, wi = wt[i][q].y;
+                sre[q] = fmaf(wr, gr, fmaf(-wi, gi, sre[q]));
+                sim[q] = fmaf(wr, gi, fmaf(wi, gr, sim[q]));
+            }
+    }
+}
+
+__device__ __forceinline__ void hist_add(uint32_t* h32, int32_t x, int T, int& bad) {
+    if ((uint32_t)x >= (uint32_t)T) {
+        ++bad;
+        x = fold_stamp(x, T);
+    }
+    atomicAdd(&h32[x >> 2], 1u << ((x & 3) << 3));
+}
+
+__device__ __forceinline__ void zero_hist_wave(uint8_t* hist, int bytes, int lane) {
+    for (int o = lane * 16; o < bytes; o += kWave * 16)
+        *reinterpret_cast<uint4*>(hist + o) = make_uint4(0, 0, 0, 0);
+}
+
+// A run of stamps a wave streams: stamps [c0, c1) of pixel pix, whose clamped range is [pb, pe)
+// (raw_e: its unclamped end offset, the next pixel's start).  `last` marks the pixel's final
+// run; an empty pixel is one empty run.  Every field is wave-uniform.
+struct Run {
+    int64_t pix, c0, c1, pb, pe, raw_e;
+    bool last, valid;
+};
+
+template <int Q, int MTT, int U>
+__global__ __launch_bounds__(kBinThreads) void sketch_binned_kernel(
+    const int32_t* __restrict__ stamps, int64_t N, const int64_t* __restrict__ offsets, int P, int T, int m,
+    const float2* __restrict__ table, float* __restrict__ z, int32_t* __restrict__ nout, double* __restrict__ acc,
+    int64_t* __restrict__ nacc, int32_t* __restrict__ err) {
+    constexpr int HB = MTT * 16 * kRowBins;                   // histogram bytes per wave
+    constexpr int C = U * kWave;                              // stamps per run
+    __shared__ __align__(16) uint8_t s_hist[kBinWaves][HB];
+    __shared__ float2 s_w[MTT * 16 * 16 * Q];
+    __shared__ float2 s_red[kBinWaves][4][Q][16];
+
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+    const int J = (T + kRowBins - 1) / kRowBins;
+    const int MT = (J + 15) / 16;
+    const int hbytes = MT * 16 * kRowBins;
+    uint8_t* hist = s_hist[wave];
+    uint32_t* h32 = reinterpret_cast<uint32_t*>(hist);
+
+    // twiddles W_l[j] (zero for l > m and for the padding rows j >= J), shared by the waves
+    for (int idx = threadIdx.x; idx < MT * 16 * 16 * Q; idx += kBinThreads) {
+        const int j = idx / (16 * Q), l = idx % (16 * Q) + 1;
+        float2 w = make_float2(0.f, 0.f);
+        if (l <= m && j < J) w = table[(int)(((int64_t)l * kRowBins * j) % T)];
+        s_w[idx] = w;
+    }
+    zero_hist_wave(hist, hbytes, lane);
+    VFrags<Q> V;
+    load_vfrags<Q>(V, table, T, m, lane);
+    __syncthreads();                                          // s_w complete; the only barrier
+
+    const int64_t gw = (int64_t)blockIdx.x * kBinWaves + wave, nw = (int64_t)gridDim.x * kBinWaves;
+    const int64_t p0 = (int64_t)P * gw / nw, p1 = (int64_t)P * (gw + 1) / nw;
+    if (p0 >= p1) return;                                     // whole wave
+    int bad_stamps = 0, bad_offsets = 0;
+
+    auto pixel_run = [&](int64_t pix, int64_t raw_b, int64_t raw_e) {
+        int64_t b = raw_b < 0 ? 0 : (raw_b > N ? N : raw_b);
+        int64_t e = raw_e < 0 ? 0 : (raw_e > N ? N : raw_e);
+        if (e < b || b != raw_b || e != raw_e) {              // clamped or decreasing (as the photon pass)
+            ++bad_offsets;
+            if (e < b) e = b;
+        }
+        const int64_t c1 = b + C < e ? b + C : e;
+        return Run{pix, b, c1, b, e, raw_e, c1 == e, true};
+    };
+    auto next = [&](const Run& d) {
+        if (!d.valid) return d;
+        if (!d.last) {
+            const int64_t c1 = d.c1 + C < d.pe ? d.c1 + C : d.pe;
+            return Run{d.pix, d.c1, c1, d.pb, d.pe, d.raw_e, c1 == d.pe, true};
+        }
+        if (d.pix + 1 >= p1) {
+            Run r = d;
+            r.valid = false;
+            return r;
+        }
+        return pixel_run(d.pix + 1, d.raw_e, uniform64(offsets[d.pix + 2]));
+    };
+    // Every run issues its U loads, valid or not, with indices clamped into the stamp array: the
+    // compiler then knows exactly which loads are younger than a run's data and waits for that
+    // run alone.  Lanes past the run's end hold values that are never used.  With no stamps at
+    // all, `src` is a dummy readable address (the offsets array).
+    const int32_t* src = N > 0 ? stamps : reinterpret_cast<const int32_t*>(offsets);
+    const int64_t last = N > 0 ? N - 1 : 0;
+    auto issue = [&](int32_t* v, const Run& d) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = d.c0 + lane + (int64_t)u * kWave;
+            v[u] = src[i < last ? i : last];
+        }
+    };
+
+    // All of pixel d.pix is in the histogram: contract, check, emit, clear.
+    auto complete = [&](const Run& d) {
+        const int64_t pix = d.pix, count = d.pe - d.pb;
+        int64_t count_total = count;
+        if (acc) count_total = nacc[pix] + count;
+        float sre[Q], sim[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) sre[q] = sim[q] = 0.f;
+        if (count > 0) {
+            uint32_t bsum = 0;
+            int64_t dc = T % 1024 == 0 ? (count + T / 2) / T : 0;   // nearest mean count per bin
+            if (dc > kSafeChunk) dc = kSafeChunk;
+            mfma_tiles<Q>(hist, s_w, V, MT, lane, (int)dc, sre, sim, bsum);
+            zero_hist_wave(hist, hbytes, lane);               // after this wave's reads (LDS is in order)
+            if (count > kSafeChunk && (int64_t)wave_sum_u32(bsum) != count) {
+                // Some bin passed 255: redo the pixel in chunks that cannot overflow (rare).
+#pragma unroll
+                for (int q = 0; q < Q; ++q) sre[q] = sim[q] = 0.f;
+                for (int64_t c0 = d.pb; c0 < d.pe; c0 += kSafeChunk) {
+                    const int64_t ce = c0 + kSafeChunk < d.pe ? c0 + kSafeChunk : d.pe;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t i = c0 + lane + (int64_t)u * kWave;
+                        if (i < ce) {
+                            int dummy = 0;
+                            hist_add(h32, stamps[i], T, dummy);   // folds were counted in the first pass
+                        }
+                    }
+                    uint32_t unused = 0;
+                    mfma_tiles<Q>(hist, s_w, V, MT, lane, 0, sre, sim, unused);
+                    zero_hist_wave(hist, hbytes, lane);
+                }
+            }
+        }
+        // sum over the four row groups g, fixed order
+        const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) s_red[wave][g][q][c] = make_float2(sre[q], sim[q]);
+        if (lane < 16 * Q) {
+            const int q = lane >> 4, l = 16 * q + c + 1;
+            if (l <= m) {
+                float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+                for (int gg = 0; gg < 4; ++gg) {
+                    const float2 v = s_red[wave][gg][q][c];
+                    s0 += v.x;
+                    s1 += v.y;
+                }
+                const int64_t o = pix * m * 2 + 2 * (l - 1);
+                if (acc) {
+                    const double a0 = acc[o] + (double)s0, a1 = acc[o + 1] + (double)s1;
+                    acc[o] = a0;
+                    acc[o + 1] = a1;
+                    z[o] = count_total > 0 ? (float)(a0 / (double)count_total) : 0.f;
+                    z[o + 1] = count_total > 0 ? (float)(a1 / (double)count_total) : 0.f;
+                } else {
+                    z[o] = count > 0 ? (float)((double)s0 / (double)count) : 0.f;
+                    z[o + 1] = count > 0 ? (float)((double)s1 / (double)count) : 0.f;
+                }
+            }
+        }
+        if (lane == 0) {
+            if (acc) nacc[pix] = count_total;
+            nout[pix] = (int32_t)(count_total > 0x7fffffff ? 0x7fffffff : count_total);
+        }
+    };
+    auto consume = [&](const int32_t* v, const Run& d) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (d.c0 + lane + (int64_t)u * kWave < d.c1) hist_add(h32, v[u], T, bad_stamps);
+        if (d.last) complete(d);
+    };
+
+    Run dx = pixel_run(p0, uniform64(offsets[p0]), uniform64(offsets[p0 + 1]));
+    Run dy = next(dx);
+    int32_t X[U], Y[U];
+    issue(X, dx);
+    issue(Y, dy);
+    // One exit, after both issues: every path into the loop head then has X's loads older than
+    // Y's, so consuming X waits for X alone.
+    while (true) {
+        consume(X, dx);
+        const Run dz = next(dy);
+        issue(X, dz);
+        if (dy.valid) consume(Y, dy);
+        const Run dw = next(dz);
+        issue(Y, dw);
+        if (!dz.valid) break;
+        dx = dz;
+        dy = dw;
+    }
+    if (err) {
+        bad_stamps = (int)wave_sum_u32((uint32_t)bad_stamps);
+        if (lane == 0 && bad_stamps) atomicAdd(&err[0], bad_stamps);
+        if (lane == 0 && bad_offsets) atomicAdd(&err[1], bad_offsets);
+    }
+}
+
+template <int Q, int MTT, int U>
+hipError_t launch_binned(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T, int m,
+                         const float2* table, float* z, int32_t* n, double* acc, int64_t* nacc, int32_t* err,
+                         hipStream_t s) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t st = hipGetDevice(&dev);
+    if (st != hipSuccess) return st;
+    st = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (st != hipSuccess) return st;
+    st = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sketch_binned_kernel<Q, MTT, U>, kBinThreads, 0);
+    if (st != hipSuccess) return st;
+    if (per_cu < 1) per_cu = 1;
+    const int64_t cap = (int64_t)cus * per_cu;
+    const int64_t need = ((int64_t)P + kBinWaves - 1) / kBinWaves;
+    const unsigned blocks = (unsigned)(need < cap ? need : cap);
+    hipLaunchKernelGGL((sketch_binned_kernel<Q, MTT, U>), dim3(blocks), dim3(kBinThreads), 0, s, stamps, N, offsets,
+                       P, T, m, table, z, n, acc, nacc, err);
+    return hipGetLastError();
+}
+
+template <int Q, int MTT>
+hipError_t launch_binned_u(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T, int m,
+                           const float2* table, float* z, int32_t* n, double* acc, int64_t* nacc, int32_t* err,
+                           hipStream_t s) {
+    // longer runs (more bytes in flight per wave) when pixels hold many photons
+    if ((double)N >= 2048.0 * (double)P)
+        return launch_binned<Q, MTT, 16>(stamps, N, offsets, P, T, m, table, z, n, acc, nacc, err, s);
+    return launch_binned<Q, MTT, 8>(stamps, N, offsets, P, T, m, table, z, n, acc, nacc, err, s);
+}
+
+}  // namespace
+
+hipError_t launch_sketch_binned(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T, int m,
+                                const float2* table, float* z, int32_t* n, double* acc, int64_t* nacc, int32_t* err,
+                                hipStream_t s) {
+    const bool q1 = m <= 16, t1 = T <= 4 * 16 * kRowBins;
+    if (q1 && t1) return launch_binned_u<1, 4>(stamps, N, offsets, P, T, m, table, z, n, acc, nacc, err, s);
+    if (q1) return launch_binned_u<1, 8>(stamps, N, offsets, P, T, m, table, z, n, acc, nacc, err, s);
+    if (t1) return launch_binned_u<2, 4>(stamps, N, offsets, P, T, m, table, z, n, acc, nacc, err, s);
+    return launch_binned_u<2, 8>(stamps, N, offsets, P, T, m, table, z, n, acc, nacc, err, s);
+}
+
+}  // namespace srt3d

@@ -75,12 +75,8 @@ __device__ __forceinline__ void reduce_scatter(float* v, int lane, int& base) {
     }
 }
 
-// One pass over a pixel's photons for harmonics l0+1 .. l0+MC.  Harmonics come in pairs: the
-// first of each pair is read from the table at its exact phase k = (l x) mod T (advanced by 2x
-// per pair), the second is that entry times exp(i w_1 x), the table entry at k = x, so each
-// photon costs MC/2 table reads (LDS bandwidth, with its data-dependent bank conflicts, is the
-// binding resource) and two extra multiply-adds per pair.
-// Add photon x's harmonics l0+1 .. l0+MC into v.
+// Add photon x's harmonics l0+1 .. l0+MC into v (odd ones from the table, even ones as the
+// preceding entry times exp(i w_1 x)).
 template <int MC, bool POW2>
 __device__ __forceinline__ void add_photon(float* v, int32_t x, int l0, int T, uint32_t T8, const char* tab) {
     const uint32_t x8 = (uint32_t)x << 3;
@@ -122,7 +118,13 @@ __device__ __forceinline__ void add_photon(float* v, int32_t x, int l0, int T, u
 // photon costs MC/2 table reads (LDS bandwidth, with its data-dependent bank conflicts, is a
 // binding resource) and two extra multiply-adds per pair.  Stamps are loaded kU per lane at a
 // time, the next group while the current one is summed, to keep loads in flight.
+//
+// Summation is two-level so that FP32 rounding stays bounded for any photon count: a lane's
+// run of at most kSeg * kU photons goes into v, the group's runs are combined by the
+// reduce-scatter, and the segments are added into f (KEEP values per lane).  A run of k equal
+// terms rounds to within about k 2^-25 relative; k <= 128 keeps that near 4e-6.
 constexpr int kU = 4;
+constexpr int kSeg = 32;
 
 template <int MC, int G, bool POW2>
 __device__ __forceinline__ void sketch_pass(const int32_t* __restrict__ stamps, int64_t b, int64_t e, int lane,
@@ -130,17 +132,23 @@ __device__ __forceinline__ void sketch_pass(const int32_t* __restrict__ stamps, 
                                             int64_t count_total, float* __restrict__ zrow,
                                             double* __restrict__ accrow, int& bad) {
     constexpr int V = 2 * MC;
+    constexpr int KEEP = V >= G ? V / G : 1;
+    constexpr int DUP = V >= G ? 1 : G / V;       // lanes holding identical sums
     const char* tab = reinterpret_cast<const char*>(s_table);
-    float v[V];
+    float v[V], f[KEEP];
 #pragma unroll
     for (int i = 0; i < V; ++i) v[i] = 0.f;
+#pragma unroll
+    for (int i = 0; i < KEEP; ++i) f[i] = 0.f;
     const int sub = lane & (G - 1);
     int32_t cur[kU], nxt[kU];
-    int64_t p = b + sub;
 #pragma unroll
-    for (int u = 0; u < kU; ++u) cur[u] = (p + u * G < e) ? stamps[p + u * G] : 0;
-    while (p < e) {
-        const int64_t pn = p + kU * G;
+    for (int u = 0; u < kU; ++u) cur[u] = (b + sub + u * G < e) ? stamps[b + sub + u * G] : 0;
+    int base = 0, run = 0;
+    // q0 is the same for every lane of the group, so a segment flush (which shuffles within the
+    // group) is taken by all of its lanes together.
+    for (int64_t q0 = b; q0 < e; q0 += kU * G) {
+        const int64_t p = q0 + sub, pn = p + kU * G;
 #pragma unroll
         for (int u = 0; u < kU; ++u) nxt[u] = (pn + u * G < e) ? stamps[pn + u * G] : 0;
 #pragma unroll
@@ -156,25 +164,33 @@ __device__ __forceinline__ void sketch_pass(const int32_t* __restrict__ stamps, 
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
-        p = pn;
+        if (++run == kSeg && q0 + kU * G < e) {
+            base = 0;
+            reduce_scatter<V, G / 2>(v, lane, base);
+#pragma unroll
+            for (int i = 0; i < KEEP; ++i) f[i] += v[i];
+#pragma unroll
+            for (int i = 0; i < V; ++i) v[i] = 0.f;
+            run = 0;
+        }
     }
-    int base = 0;
+    base = 0;
     reduce_scatter<V, G / 2>(v, lane, base);
-    constexpr int KEEP = V >= G ? V / G : 1;
-    constexpr int DUP = V >= G ? 1 : G / V;       // lanes holding identical sums
+#pragma unroll
+    for (int i = 0; i < KEEP; ++i) f[i] += v[i];
     if ((sub & (DUP - 1)) != 0) return;
     const int o = 2 * l0 + base;
     if (accrow) {
 #pragma unroll
         for (int i = 0; i < KEEP; ++i) {
-            const double a = accrow[o + i] + (double)v[i];
+            const double a = accrow[o + i] + (double)f[i];
             accrow[o + i] = a;
             zrow[o + i] = count_total > 0 ? (float)(a / (double)count_total) : 0.f;
         }
     } else {
 #pragma unroll
         for (int i = 0; i < KEEP; ++i)
-            zrow[o + i] = count > 0 ? (float)((double)v[i] / (double)count) : 0.f;
+            zrow[o + i] = count > 0 ? (float)((double)f[i] / (double)count) : 0.f;
     }
 }
 

@@ -75,6 +75,11 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.srt3d_sketch(fake, 10, fake, 4, 1024, 4, fake, fake, fake, fake, None, None, None) == -1
     assert lib.srt3d_sketch(fake, -1, fake, 4, 1024, 4, fake, fake, fake, None, None, None, None) == -1
     assert lib.srt3d_sketch(fake, 10, fake, 4, 1024, 4, fake, VP(0x1004), fake, None, None, None, None) == -1
+    for args in ((fake, 10, fake, 0, 1024, 4), (fake, 10, fake, 4, 1024, 33), (fake, 10, fake, 4, 16384, 4),
+                 (fake, -1, fake, 4, 1024, 4)):
+        assert lib.srt3d_sketch_binned(*args, fake, fake, fake, None, None, None, None) == -1
+    assert lib.srt3d_sketch_binned(fake, 10, fake, 4, 1024, 4, None, fake, fake, None, None, None, None) == -1
+    assert lib.srt3d_sketch_binned(fake, 10, fake, 4, 1024, 4, fake, fake, fake, fake, None, None, None) == -1
     assert lib.srt3d_phase_table(1, fake, None) == -1
     # histogram: T not a multiple of 32, m > 32, bad precision, misaligned pointer, small workspace
     assert lib.srt3d_hist_prepare(1000, 4, 0, fake, 1 << 20, None) == -1
