@@ -27,9 +27,15 @@ FLAGS = [
 ]
 
 
+# Per-source additions: the binned sketch reads every MFMA result with VALU right away, so its
+# accumulators go in VGPRs rather than AGPRs (no v_accvgpr_read per element).
+EXTRA = {"binned.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, src + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-x", "hip", "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src),
+           "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -83,6 +83,7 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) {
 template <int Q>
 struct VFrags {
     v8h hi[2][Q][2], lo[2][Q][2];     // [k-step][q][re/im]
+    float2 wl[4][Q];                  // W_l[4 g + i]: the lane's row twiddles within a tile
 };
 
 template <int Q>
@@ -108,12 +109,64 @@ __device__ __forceinline__ void load_vfrags(VFrags<Q>& V, const float2* __restri
                 V.lo[ks][q][1][e] = split_lo(sv);
             }
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            V.wl[i][q] = l <= m ? table[(int)(((int64_t)l * kRowBins * (4 * g + i)) % T)] : make_float2(0.f, 0.f);
+    }
+}
+
+// One M-tile (rows j = 16 mt .. 16 mt + 15) of the product, added into sre/sim.  The split
+// V = V1 + 2^-11 V2 runs in one accumulator: the V2 products use A scaled by 2^-11 (exact: the
+// entries are small integers).  The twiddle of row j = 16 mt + 4 g + i factors exactly as
+// W_l[16 mt] * W_l[4 g + i]: the lane's four row twiddles W_l[4 g + i] stay in registers, the
+// tile's common factor W_l[16 mt] is one LDS read per lane and tile.
+template <int Q>
+__device__ __forceinline__ void mfma_tile(const uint8_t* hist, const float2* s_wm, const VFrags<Q>& V, int mt,
+                                          int lane, v2h bias, float* sre, float* sim, uint32_t& bsum) {
+    const int c = lane & 15, g = lane >> 4;
+    const uint8_t* row = hist + (16 * mt + c) * kRowBins + 8 * g;
+    const uint2 w0 = *reinterpret_cast<const uint2*>(row);
+    const uint2 w1 = *reinterpret_cast<const uint2*>(row + 32);
+    float2 wm[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) wm[q] = s_wm[mt * (16 * Q) + 16 * q + c];
+    bsum = __builtin_amdgcn_sad_u8(w0.x, 0u, bsum);
+    bsum = __builtin_amdgcn_sad_u8(w0.y, 0u, bsum);
+    bsum = __builtin_amdgcn_sad_u8(w1.x, 0u, bsum);
+    bsum = __builtin_amdgcn_sad_u8(w1.y, 0u, bsum);
+    const v8h A0 = bytes_to_h8(w0.x, w0.y, bias), A1 = bytes_to_h8(w1.x, w1.y, bias);
+    const _Float16 sc = (_Float16)(1.0f / 2048.0f);
+    const v8h S0 = A0 * sc, S1 = A1 * sc;
+    v4f acc[Q][2];
+    const v4f zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            acc[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, V.hi[0][q][p], zero, 0, 0, 0);
+            acc[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(S0, V.lo[0][q][p], acc[q][p], 0, 0, 0);
+            acc[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, V.hi[1][q][p], acc[q][p], 0, 0, 0);
+            acc[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(S1, V.lo[1][q][p], acc[q][p], 0, 0, 0);
+        }
+    // output element i of a tile: row 4 g + i, column c
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        float ur = 0.f, ui = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float gr = acc[q][0][i], gi = acc[q][1][i];
+            const float wr = V.wl[i][q].x, wi = V.wl[i][q].y;
+            ur = fmaf(wr, gr, fmaf(-wi, gi, ur));
+            ui = fmaf(wr, gi, fmaf(wi, gr, ui));
+        }
+        sre[q] = fmaf(wm[q].x, ur, fmaf(-wm[q].y, ui, sre[q]));
+        sim[q] = fmaf(wm[q].x, ui, fmaf(wm[q].y, ur, sim[q]));
     }
 }
 
 // Add the contribution of the histogram minus a constant `dc` in every bin to the lane's partial
 // sums sre/sim (harmonic 16 q + c + 1, summed over the lane's rows 16 mt + 4 g + i) and the
-// lane's raw byte sum to bsum.  s_w[j][16 Q] holds W_l[j] for l = 1 .. 16 Q.
+// lane's raw byte sum to bsum.
 //
 // The constant changes nothing exactly: the sum of exp(i w_l t) over all T bins is zero for
 // 0 < l < T.  With dc near the mean count it removes the common level of the bins, which would
@@ -122,53 +175,11 @@ __device__ __forceinline__ void load_vfrags(VFrags<Q>& V, const float2* __restri
 // needs every A element to be a real bin (T a multiple of 1024, no padding rows); otherwise
 // the caller passes dc = 0.
 template <int Q>
-__device__ __forceinline__ void mfma_tiles(const uint8_t* hist, const float2* s_w, const VFrags<Q>& V, int MT,
+__device__ __forceinline__ void mfma_tiles(const uint8_t* hist, const float2* s_wm, const VFrags<Q>& V, int MT,
                                            int lane, int dc, float* sre, float* sim, uint32_t& bsum) {
-    const int c = lane & 15, g = lane >> 4;
     const _Float16 bh = (_Float16)(float)(-1024 - dc);
     const v2h bias = {bh, bh};
-    for (int mt = 0; mt < MT; ++mt) {
-        const uint8_t* row = hist + (16 * mt + c) * kRowBins + 8 * g;
-        const uint2 w0 = *reinterpret_cast<const uint2*>(row);
-        const uint2 w1 = *reinterpret_cast<const uint2*>(row + 32);
-        float2 wt[4][Q];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int q = 0; q < Q; ++q) wt[i][q] = s_w[(16 * mt + 4 * g + i) * (16 * Q) + 16 * q + c];
-        bsum = __builtin_amdgcn_sad_u8(w0.x, 0u, bsum);
-        bsum = __builtin_amdgcn_sad_u8(w0.y, 0u, bsum);
-        bsum = __builtin_amdgcn_sad_u8(w1.x, 0u, bsum);
-        bsum = __builtin_amdgcn_sad_u8(w1.y, 0u, bsum);
-        const v8h A0 = bytes_to_h8(w0.x, w0.y, bias), A1 = bytes_to_h8(w1.x, w1.y, bias);
-        v4f hi[Q][2], lo[Q][2];
-        const v4f zero = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-#pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                hi[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, V.hi[0][q][p], zero, 0, 0, 0);
-                lo[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, V.lo[0][q][p], zero, 0, 0, 0);
-            }
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-#pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                hi[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, V.hi[1][q][p], hi[q][p], 0, 0, 0);
-                lo[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, V.lo[1][q][p], lo[q][p], 0, 0, 0);
-            }
-        // output element i of a tile: row 4 g + i, column c
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float gr = fmaf(lo[q][0][i], 1.0f / 2048.0f, hi[q][0][i]);
-                const float gi = fmaf(lo[q][1][i], 1.0f / 2048.0f, hi[q][1][i]);
-                const float wr = wt[i][q].x, wi = wt[i][q].y;
-                sre[q] = fmaf(wr, gr, fmaf(-wi, gi, sre[q]));
-                sim[q] = fmaf(wr, gi, fmaf(wi, gr, sim[q]));
-            }
-    }
+    for (int mt = 0; mt < MT; ++mt) mfma_tile<Q>(hist, s_wm, V, mt, lane, bias, sre, sim, bsum);
 }
 
 __device__ __forceinline__ void hist_add(uint32_t* h32, int32_t x, int T, int& bad) {
@@ -200,27 +211,27 @@ __global__ __launch_bounds__(kBinThreads) void sketch_binned_kernel(
     constexpr int HB = MTT * 16 * kRowBins;                   // histogram bytes per wave
     constexpr int C = U * kWave;                              // stamps per run
     __shared__ __align__(16) uint8_t s_hist[kBinWaves][HB];
-    __shared__ float2 s_w[MTT * 16 * 16 * Q];
+    __shared__ float2 s_wm[MTT * 16 * Q];
     __shared__ float2 s_red[kBinWaves][4][Q][16];
 
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+    // the wave index is uniform across the wave: say so, so that everything derived from it (the
+    // pixel range, each run, the offsets loads) stays in scalar registers and scalar loads
+    const int lane = threadIdx.x & (kWave - 1), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int J = (T + kRowBins - 1) / kRowBins;
     const int MT = (J + 15) / 16;
     const int hbytes = MT * 16 * kRowBins;
     uint8_t* hist = s_hist[wave];
     uint32_t* h32 = reinterpret_cast<uint32_t*>(hist);
 
-    // twiddles W_l[j] (zero for l > m and for the padding rows j >= J), shared by the waves
-    for (int idx = threadIdx.x; idx < MT * 16 * 16 * Q; idx += kBinThreads) {
-        const int j = idx / (16 * Q), l = idx % (16 * Q) + 1;
-        float2 w = make_float2(0.f, 0.f);
-        if (l <= m && j < J) w = table[(int)(((int64_t)l * kRowBins * j) % T)];
-        s_w[idx] = w;
+    // tile twiddle factors W_l[16 mt] (zero for l > m), shared by the waves
+    for (int idx = threadIdx.x; idx < MT * 16 * Q; idx += kBinThreads) {
+        const int mt = idx / (16 * Q), l = idx % (16 * Q) + 1;
+        s_wm[idx] = l <= m ? table[(int)(((int64_t)l * 16 * kRowBins * mt) % T)] : make_float2(0.f, 0.f);
     }
     zero_hist_wave(hist, hbytes, lane);
     VFrags<Q> V;
     load_vfrags<Q>(V, table, T, m, lane);
-    __syncthreads();                                          // s_w complete; the only barrier
+    __syncthreads();                                          // s_wm complete; the only barrier
 
     const int64_t gw = (int64_t)blockIdx.x * kBinWaves + wave, nw = (int64_t)gridDim.x * kBinWaves;
     const int64_t p0 = (int64_t)P * gw / nw, p1 = (int64_t)P * (gw + 1) / nw;
@@ -257,10 +268,13 @@ __global__ __launch_bounds__(kBinThreads) void sketch_binned_kernel(
     const int32_t* src = N > 0 ? stamps : reinterpret_cast<const int32_t*>(offsets);
     const int64_t last = N > 0 ? N - 1 : 0;
     auto issue = [&](int32_t* v, const Run& d) {
+        const int64_t base = d.c0 < last ? d.c0 : last;
+        const uint32_t lim = (uint32_t)(last - base < (int64_t)C ? last - base : (int64_t)C);
+        const int32_t* rp = src + base;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t i = d.c0 + lane + (int64_t)u * kWave;
-            v[u] = src[i < last ? i : last];
+            const uint32_t o = (uint32_t)(lane + u * kWave);
+            v[u] = rp[o < lim ? o : lim];
         }
     };
 
@@ -274,9 +288,10 @@ __global__ __launch_bounds__(kBinThreads) void sketch_binned_kernel(
         for (int q = 0; q < Q; ++q) sre[q] = sim[q] = 0.f;
         if (count > 0) {
             uint32_t bsum = 0;
-            int64_t dc = T % 1024 == 0 ? (count + T / 2) / T : 0;   // nearest mean count per bin
+            // about the mean count per bin (any integer is exact; this one keeps the bins small)
+            int dc = T % 1024 == 0 ? (int)((float)count * (1.0f / (float)T) + 0.5f) : 0;
             if (dc > kSafeChunk) dc = kSafeChunk;
-            mfma_tiles<Q>(hist, s_w, V, MT, lane, (int)dc, sre, sim, bsum);
+            mfma_tiles<Q>(hist, s_wm, V, MT, lane, dc, sre, sim, bsum);
             zero_hist_wave(hist, hbytes, lane);               // after this wave's reads (LDS is in order)
             if (count > kSafeChunk && (int64_t)wave_sum_u32(bsum) != count) {
                 // Some bin passed 255: redo the pixel in chunks that cannot overflow (rare).
@@ -293,7 +308,7 @@ __global__ __launch_bounds__(kBinThreads) void sketch_binned_kernel(
                         }
                     }
                     uint32_t unused = 0;
-                    mfma_tiles<Q>(hist, s_w, V, MT, lane, 0, sre, sim, unused);
+                    mfma_tiles<Q>(hist, s_wm, V, MT, lane, 0, sre, sim, unused);
                     zero_hist_wave(hist, hbytes, lane);
                 }
             }
@@ -331,9 +346,10 @@ __global__ __launch_bounds__(kBinThreads) void sketch_binned_kernel(
         }
     };
     auto consume = [&](const int32_t* v, const Run& d) {
+        const int len = (int)(d.c1 - d.c0);                   // <= C
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (d.c0 + lane + (int64_t)u * kWave < d.c1) hist_add(h32, v[u], T, bad_stamps);
+            if (lane + u * kWave < len) hist_add(h32, v[u], T, bad_stamps);
         if (d.last) complete(d);
     };
 
