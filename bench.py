@@ -4,9 +4,13 @@
 One step = the photon sketch of a 256x256 frame (T = 4096 bins, ~1000 photons per pixel,
 SBR = 1, m = 16 harmonics; ~6.6e7 int32 stamps resident in HBM) followed by the SRT3D
 reconstruction of that sketch (initialisation, 50 iterations of data step + depth denoiser +
-intensity denoiser, background and output).  Prints one JSON line.
+intensity denoiser, background and output).  Prints one JSON line.  The sketch runs on the
+binned path by default (per-pixel histogram on the FP16 matrix cores); --sketch photon times
+the photon-parallel FP32 pass instead.  Both meet the same tolerance against the oracle, and
+the line reports the other one's time beside the timed steps.
 
-    python bench.py [--steps K] [--warmup W] [--workload throughput] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload throughput] [--sketch binned|photon]
+                    [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -23,8 +27,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "photons sketched/s + SRT3D frames/s (fraction of HBM roofline); p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sketch_photons_throughput_traffic.md")
-SKETCH_SRC = os.path.join(ROOT, "paper_2203_00952_amd", "csrc", "sketch.hip")
+# per sketch method: (kernel name, its source file, the committed HBM-counter summary)
+SKETCH_KERNELS = {
+    "binned": ("sketch_binned_kernel", "binned.hip", "sketch_binned_{w}_traffic.md"),
+    "photon": ("sketch_photons_kernel", "sketch.hip", "sketch_photons_{w}_traffic.md"),
+}
 
 
 def parse():
@@ -33,6 +40,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="throughput")
+    ap.add_argument("--sketch", default="binned", choices=sorted(SKETCH_KERNELS),
+                    help="sketch path timed in the step (both meet the same oracle tolerance)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=96, help="serving workload: number of requests")
     ap.add_argument("--budget-gib", type=float, default=4.0, help="serving workload: HBM budget")
@@ -41,14 +50,16 @@ def parse():
     return ap.parse_args()
 
 
-def sketch_traffic(launch_bytes: float):
+def sketch_traffic(method: str, workload: str):
     """HBM bytes per sketch launch from the committed counter summary, if it describes the
     current kernel source (else None)."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+    _, src, summary = SKETCH_KERNELS[method]
+    path = os.path.join(ROOT, "profiles", summary.format(w=workload))
+    if not os.path.exists(path):
         return None
-    text = open(TRAFFIC_SUMMARY).read()
-    sha = hashlib.sha256(open(SKETCH_SRC, "rb").read()).hexdigest()
-    m_sha = re.search(r"sketch\.hip sha256:\s*([0-9a-f]{64})", text)
+    text = open(path).read()
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2203_00952_amd", "csrc", src), "rb").read()).hexdigest()
+    m_sha = re.search(re.escape(src) + r" sha256:\s*([0-9a-f]{64})", text)
     m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not m_sha or not m_b or m_sha.group(1) != sha:
         return None
@@ -251,7 +262,7 @@ def main():
     def step(ev=None):
         if ev:
             ev[0].record(stream)
-        srt.sketch(frame.stamps, frame.offsets, T, m, z=z, n=n, table=table)
+        srt.sketch(frame.stamps, frame.offsets, T, m, z=z, n=n, table=table, method=args.sketch)
         if ev:
             ev[1].record(stream)
         rec.reconstruct(z, n, irf, frame.irf_origin, out=out)
@@ -276,7 +287,22 @@ def main():
     # algorithmic bytes of one sketch launch: stamps + offsets in, sketch + counts out
     alg_bytes = 4.0 * N + 8.0 * (P + 1) + 8.0 * m * P + 4.0 * P
     achieved = alg_bytes / (sk_ms.mean() * 1e-3) / 1e9
-    traffic = sketch_traffic(alg_bytes)
+    traffic = sketch_traffic(args.sketch, w.name)
+    kernel = SKETCH_KERNELS[args.sketch][0]
+
+    # the other sketch path on the same frame, for reference (outside the timed steps)
+    other = "photon" if args.sketch == "binned" else "binned"
+    z2 = torch.empty_like(z)
+    n2 = torch.empty_like(n)
+    srt.sketch(frame.stamps, frame.offsets, T, m, z=z2, n=n2, table=table, method=other)
+    e_o = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e_o[0].record(stream)
+    for _ in range(3):
+        srt.sketch(frame.stamps, frame.offsets, T, m, z=z2, n=n2, table=table, method=other)
+    e_o[1].record(stream)
+    torch.cuda.synchronize()
+    other_ms = e_o[0].elapsed_time(e_o[1]) / 3
+    del z2, n2
     res = {
         "metric": METRIC,
         "value": args.steps / wall,
@@ -288,19 +314,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f16x2-split products, f32 accumulation" if args.sketch == "binned" else "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "pixels": P, "rows": spec.rows, "cols": spec.cols, "T": T, "m": m,
                    "K_max": w.K_max, "iters": w.iters, "photons": N, "photons_per_pixel": spec.lam,
                    "sbr": spec.sbr, "irf_sigma_bins": spec.sigma},
         "photons_per_s": N * args.steps / wall,
         "sketch_photons_per_s": N / (sk_ms.mean() * 1e-3),
+        "sketch_method": args.sketch,
+        "other_sketch": {"method": other, "ms": other_ms, "photons_per_s": N / (other_ms * 1e-3)},
         "sketch_ms": {"mean": float(sk_ms.mean()), "p50": float(np.percentile(sk_ms, 50)),
                       "p99": float(np.percentile(sk_ms, 99))},
         "srt3d_ms": {"mean": float(rc_ms.mean()), "p50": float(np.percentile(rc_ms, 50)),
                      "p99": float(np.percentile(rc_ms, 99))},
         "latency_ms": {"p50": float(np.percentile(st_ms, 50)), "p99": float(np.percentile(st_ms, 99))},
-        "roofline": {"bound": "hbm", "kernel": "sketch_photons_kernel", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes},
     }

@@ -190,6 +190,15 @@ __device__ __forceinline__ void hist_add(uint32_t* h32, int32_t x, int T, int& b
     atomicAdd(&h32[x >> 2], 1u << ((x & 3) << 3));
 }
 
+// Power-of-two T: the fold is a mask (two's complement makes x & (T - 1) the mathematical
+// modulus for negative x too) and the bad-stamp count is a compare, so no branch per stamp.
+__device__ __forceinline__ void hist_add_pow2(uint32_t* h32, int32_t x, uint32_t tmask, int& bad) {
+    const uint32_t xu = (uint32_t)x;
+    bad += xu > tmask ? 1 : 0;
+    const uint32_t xf = xu & tmask;
+    atomicAdd(&h32[xf >> 2], 1u << ((xf & 3) << 3));
+}
+
 __device__ __forceinline__ void zero_hist_wave(uint8_t* hist, int bytes, int lane) {
     for (int o = lane * 16; o < bytes; o += kWave * 16)
         *reinterpret_cast<uint4*>(hist + o) = make_uint4(0, 0, 0, 0);
@@ -345,11 +354,22 @@ __global__ __launch_bounds__(kBinThreads) void sketch_binned_kernel(
             nout[pix] = (int32_t)(count_total > 0x7fffffff ? 0x7fffffff : count_total);
         }
     };
+    const bool pow2 = (T & (T - 1)) == 0;
+    const uint32_t tmask = (uint32_t)T - 1u;
     auto consume = [&](const int32_t* v, const Run& d) {
         const int len = (int)(d.c1 - d.c0);                   // <= C
+        if (pow2 && len == C) {                               // full run: no guards, no branches
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (lane + u * kWave < len) hist_add(h32, v[u], T, bad_stamps);
+            for (int u = 0; u < U; ++u) hist_add_pow2(h32, v[u], tmask, bad_stamps);
+        } else if (pow2) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (lane + u * kWave < len) hist_add_pow2(h32, v[u], tmask, bad_stamps);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (lane + u * kWave < len) hist_add(h32, v[u], T, bad_stamps);
+        }
         if (d.last) complete(d);
     };
 
