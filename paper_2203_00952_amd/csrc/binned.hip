@@ -78,6 +78,19 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Byte layout of a 64-bin histogram row: bin r sits in word r & 15, byte r >> 4, so the ~20
+// consecutive bins under a surface's return land in different words (and banks) instead of
+// five shared words; the byte at position p of a row holds bin row_bin(p).  The contraction
+// only needs every A element and its B element to name the same bin, so the V fragments are
+// built with the same permutation.
+__device__ __forceinline__ int row_bin(int p) { return 16 * (p & 3) + (p >> 2); }
+
+__device__ __forceinline__ void bin_add(uint32_t* h32, uint32_t x) {
+    // byte address (x & ~63) + 4 (x & 15) + (x >> 4 & 3): word (x & ~63) / 4 + (x & 15)
+    const uint32_t word = __builtin_amdgcn_ubfe(x, 0, 4) | ((x >> 2) & ~15u);
+    atomicAdd(&h32[word], 1u << ((x >> 1) & 24u));
+}
+
 // B operands: lane c = lane & 15 is column (harmonic l = 16 q + c + 1), g = lane >> 4 its
 // k group (bins r = 32 ks + 8 g .. + 7).
 template <int Q>
@@ -96,7 +109,7 @@ __device__ __forceinline__ void load_vfrags(VFrags<Q>& V, const float2* __restri
         for (int ks = 0; ks < 2; ++ks) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int r = 32 * ks + 8 * g + e;
+                const int r = row_bin(32 * ks + 8 * g + e);
                 float cv = 0.f, sv = 0.f;
                 if (l <= m) {
                     const float2 t = table[(l * r) % T];
@@ -187,7 +200,7 @@ __device__ __forceinline__ void hist_add(uint32_t* h32, int32_t x, int T, int& b
         ++bad;
         x = fold_stamp(x, T);
     }
-    atomicAdd(&h32[x >> 2], 1u << ((x & 3) << 3));
+    bin_add(h32, (uint32_t)x);
 }
 
 // Power-of-two T: the fold is a mask (two's complement makes x & (T - 1) the mathematical
@@ -196,7 +209,7 @@ __device__ __forceinline__ void hist_add_pow2(uint32_t* h32, int32_t x, uint32_t
     const uint32_t xu = (uint32_t)x;
     bad += xu > tmask ? 1 : 0;
     const uint32_t xf = xu & tmask;
-    atomicAdd(&h32[xf >> 2], 1u << ((xf & 3) << 3));
+    bin_add(h32, xf);
 }
 
 __device__ __forceinline__ void zero_hist_wave(uint8_t* hist, int bytes, int lane) {

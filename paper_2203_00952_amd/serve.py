@@ -99,14 +99,16 @@ def percentile(values, q):
 
 # ----------------------------------------------------------------------------- GPU executor
 class Request:
-    """One frame to serve: device stamps and offsets, the impulse response and its parameters."""
+    """One frame to serve: device stamps and offsets, the impulse response and its parameters.
+    `sketch` picks the sketch route ("binned" unless m > 32, where only "photon" applies)."""
 
-    def __init__(self, rid, stamps, offsets, irf, irf_origin, params, arrival=0.0):
+    def __init__(self, rid, stamps, offsets, irf, irf_origin, params, arrival=0.0, sketch=None):
         self.rid = rid
         self.stamps, self.offsets = stamps, offsets
         self.irf, self.irf_origin = irf, irf_origin
         self.params = params
         self.arrival = arrival
+        self.sketch = sketch or ("binned" if params.m <= 32 else "photon")
 
     def working_bytes(self) -> int:
         """Device memory the request holds while it runs: its photon stamps and offsets, the
@@ -139,7 +141,7 @@ class GpuExecutor:
         s = self.streams[slot]
         table = L.cached_phase_table(req.params.T, self.device)
         with torch.cuda.stream(s):
-            z, n = L.sketch(req.stamps, req.offsets, req.params.T, req.params.m, table=table)
+            z, n = L.sketch(req.stamps, req.offsets, req.params.T, req.params.m, table=table, method=req.sketch)
             rec = L.Reconstructor(req.params, self.device)
             out = rec.reconstruct(z, n, req.irf, req.irf_origin)
             ev = torch.cuda.Event()

@@ -41,6 +41,29 @@ def test_billion_sketch_sampled_pixels(billion):
     assert not bad.any()
 
 
+def test_billion_binned_sketch_sampled_pixels(billion):
+    """The binned route (the benchmark's sketch) on the same frame: sampled pixels against the
+    oracle, every pixel against the photon route within twice the rule."""
+    w, f, z, n = billion
+    print("case billion binned sketch", flush=True)
+    zb, nb = srt.sketch(f.stamps, f.offsets, w.frame.T, w.m, method="binned")
+    torch.cuda.synchronize()
+    assert torch.equal(nb, n)
+    rng = np.random.default_rng(6)
+    sel = np.sort(rng.choice(w.frame.P, 600, replace=False))
+    st_np = f.stamps.cpu().numpy()
+    zr, nr = OS.sketch(st_np, f.offsets.cpu().numpy(), w.frame.T, w.m, pixels=sel)
+    bad, err, tol = sketch_violations(to_complex(zb)[sel], zr, nr)
+    print("max err/tol", float(np.max(err / tol)))
+    assert not bad.any()
+    nn = n.cpu().numpy()
+    floor = 1.0 / np.sqrt(np.maximum(nn, 1))[:, None]
+    zp = to_complex(z)
+    d = np.abs(to_complex(zb) - zp) / (2e-5 * np.maximum(np.abs(zp), floor))
+    print("binned vs photon, max |dz| / (2 tol) =", float(d.max()))
+    assert d.max() <= 1.0
+
+
 def test_billion_stages_and_iterations(billion):
     w, f, z, n = billion
     dev = z.device

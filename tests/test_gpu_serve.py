@@ -54,7 +54,7 @@ def test_served_result_equals_direct_call():
     print("case serve_vs_direct", flush=True)
     r = _requests(dev, [0.0])[0]
     _, res, _ = serve([r], slots=2)
-    z, n = srt.sketch(r.stamps, r.offsets, r.params.T, r.params.m)
+    z, n = srt.sketch(r.stamps, r.offsets, r.params.T, r.params.m, method=r.sketch)
     out = srt.Reconstructor(r.params, dev).reconstruct(z, n, r.irf, r.irf_origin)
     torch.cuda.synchronize()
     for key in ("depth", "intensity", "active", "bg"):
