@@ -670,14 +670,14 @@ __device__ __forceinline__ void id_update(const float* rt, const bool* was_on, f
     project_capped_simplex<K>(an, keep);
 }
 
-// Load an (E x E cells) x K region with origin (gi0, gj0) into LDS; cells outside the frame are
-// inactive with depth 0.  With WITH_R the intensity n * alpha is loaded too.
+// Load an (EY x E cells) x K region with origin (gi0, gj0) into LDS (row stride E cells); cells
+// outside the frame are inactive with depth 0.  With WITH_R the intensity n * alpha is loaded too.
 template <int K, bool WITH_R>
-__device__ __forceinline__ void load_region(float* st, uint8_t* sa, float* sr, int E, int gi0, int gj0,
+__device__ __forceinline__ void load_region(float* st, uint8_t* sa, float* sr, int EY, int E, int gi0, int gj0,
                                             const IterArgs& A, const float* __restrict__ t_in,
                                             const float* __restrict__ a_in, const uint8_t* __restrict__ act_in,
                                             const int32_t* __restrict__ n) {
-    for (int idx = threadIdx.x; idx < E * E * K; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < EY * E * K; idx += blockDim.x) {
         const int k = idx % K, cell = idx / K;
         const int gi = gi0 + cell / E, gj = gj0 + cell % E;
         float tv = 0.f, rv = 0.f;
@@ -703,7 +703,7 @@ __global__ __launch_bounds__(kTile * kTile) void depth_denoise_kernel(
     __shared__ float s_t[E * E * K];
     __shared__ uint8_t s_a[E * E * K];
     const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
-    load_region<K, false>(s_t, s_a, nullptr, E, i0 - R, j0 - R, A, t_in, a_in, act_in, nullptr);
+    load_region<K, false>(s_t, s_a, nullptr, E, E, i0 - R, j0 - R, A, t_in, a_in, act_in, nullptr);
     __syncthreads();
     const int ti = threadIdx.x / kTile, tj = threadIdx.x % kTile;
     const int i = i0 + ti, j = j0 + tj;
@@ -729,7 +729,7 @@ __global__ __launch_bounds__(kTile * kTile) void intensity_denoise_kernel(
     __shared__ float s_t[E * E * K], s_r[E * E * K];
     __shared__ uint8_t s_a[E * E * K];
     const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
-    load_region<K, true>(s_t, s_a, s_r, E, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
+    load_region<K, true>(s_t, s_a, s_r, E, E, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
     __syncthreads();
     const int ti = threadIdx.x / kTile, tj = threadIdx.x % kTile;
     const int i = i0 + ti, j = j0 + tj;
@@ -753,12 +753,16 @@ __global__ __launch_bounds__(kTile * kTile) void intensity_denoise_kernel(
     }
 }
 
-// One whole iteration for a 16x16 tile: depth denoiser on the tile and an R-pixel ring (the ring
-// is recomputed by each neighbouring tile), intensity denoiser on the tile, then (DS_NEXT) the
-// next iteration's data step.  Input: the state after a data step; output: the state after the
-// next data step (or after the intensity denoiser).  One launch per iteration instead of three;
-// 1024 threads per tile so that the data step runs four lanes per pixel in one round.
-constexpr int kIterThreads = kTile * kTile * kLanesPerPixel;
+// One whole iteration for a kIterTY x kIterTX tile: depth denoiser on the tile and an R-pixel ring
+// (the ring is recomputed by each neighbouring tile), intensity denoiser on the tile, then
+// (DS_NEXT) the next iteration's data step.  Input: the state after a data step; output: the
+// state after the next data step (or after the intensity denoiser).  One launch per iteration
+// instead of three; four threads per tile pixel so that the data step runs four lanes per pixel
+// in one round.  Tiles of 8 x 16 (512 threads) let two or more blocks share a CU, so one block's
+// load and barrier waits overlap another's denoiser arithmetic.
+constexpr int kIterTY = 8, kIterTX = 16;
+constexpr int kIterPix = kIterTY * kIterTX;
+constexpr int kIterThreads = kIterPix * kLanesPerPixel;
 
 template <int K, int R, bool DS_NEXT>
 __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
@@ -766,21 +770,22 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
     const float* __restrict__ scal, const float* __restrict__ t_in, const float* __restrict__ a_in,
     const uint8_t* __restrict__ act_in, float* __restrict__ t_out, float* __restrict__ a_out,
     uint8_t* __restrict__ act_out) {
-    constexpr int E2 = kTile + 4 * R, E1 = kTile + 2 * R;
-    __shared__ float s_t2[E2 * E2 * K];          // depths after the data step, tile + 2R ring
-    __shared__ uint8_t s_a2[E2 * E2 * K];
-    __shared__ float s_td[E1 * E1 * K];          // depths after the depth denoiser, tile + R ring
-    __shared__ float s_r1[E1 * E1 * K];          // n * alpha after the data step
-    __shared__ uint8_t s_a1[E1 * E1 * K];
-    __shared__ float s_oa[kTile * kTile * K];
-    __shared__ uint8_t s_oo[kTile * kTile * K];
-    const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
-    load_region<K, false>(s_t2, s_a2, nullptr, E2, i0 - 2 * R, j0 - 2 * R, A, t_in, a_in, act_in, nullptr);
-    load_region<K, true>(s_td, s_a1, s_r1, E1, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
+    constexpr int E2 = kIterTX + 4 * R, E1 = kIterTX + 2 * R;        // region widths (row strides)
+    constexpr int E2Y = kIterTY + 4 * R, E1Y = kIterTY + 2 * R;      // region heights
+    __shared__ float s_t2[E2Y * E2 * K];         // depths after the data step, tile + 2R ring
+    __shared__ uint8_t s_a2[E2Y * E2 * K];
+    __shared__ float s_td[E1Y * E1 * K];         // depths after the depth denoiser, tile + R ring
+    __shared__ float s_r1[E1Y * E1 * K];         // n * alpha after the data step
+    __shared__ uint8_t s_a1[E1Y * E1 * K];
+    __shared__ float s_oa[kIterPix * K];
+    __shared__ uint8_t s_oo[kIterPix * K];
+    const int i0 = blockIdx.y * kIterTY, j0 = blockIdx.x * kIterTX;
+    load_region<K, false>(s_t2, s_a2, nullptr, E2Y, E2, i0 - 2 * R, j0 - 2 * R, A, t_in, a_in, act_in, nullptr);
+    load_region<K, true>(s_td, s_a1, s_r1, E1Y, E1, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
     __syncthreads();
     const float Tf = (float)A.T, invT = 1.0f / Tf, tau_z = scal[3];
     // depth denoiser on the tile + R ring
-    for (int idx = threadIdx.x; idx < E1 * E1 * K; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < E1Y * E1 * K; idx += blockDim.x) {
         const int k = idx % K, cell = idx / K;
         const int ci = cell / E1 + R, cj = cell % E1 + R;          // cell in the E2 region
         const int c2 = (ci * E2 + cj) * K + k;
@@ -789,8 +794,8 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
     }
     __syncthreads();
     // intensity denoiser on the tile (one thread per pixel)
-    if (threadIdx.x < kTile * kTile) {
-        const int ti = threadIdx.x / kTile, tj = threadIdx.x % kTile;
+    if (threadIdx.x < kIterPix) {
+        const int ti = threadIdx.x / kIterTX, tj = threadIdx.x % kIterTX;
         const int i = i0 + ti, j = j0 + tj;
         if (i < A.rows && j < A.cols) {
             float rt[K], an[K];
@@ -819,8 +824,8 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
     if constexpr (DS_NEXT) {
         __syncthreads();
         // next data step, four lanes per pixel
-        const int sub = threadIdx.x % kLanesPerPixel, pl = threadIdx.x / kLanesPerPixel;
-        const int ti = pl / kTile, tj = pl % kTile;
+        const int sub = threadIdx.x % kLanesPerPixel, pl = threadIdx.x / kLanesPerPixel;   // pl < kIterPix
+        const int ti = pl / kIterTX, tj = pl % kIterTX;
         const int pi = i0 + ti, pj = j0 + tj;
         if (pi < A.rows && pj < A.cols) {
             const int pix = pi * A.cols + pj;
@@ -925,6 +930,9 @@ static IterArgs make_args(const srt3d_params& p) {
 static inline dim3 pixel_grid(int P, int threads) { return dim3((unsigned)((P + threads - 1) / threads)); }
 static inline dim3 tile_grid(const srt3d_params& p) {
     return dim3((unsigned)((p.cols + kTile - 1) / kTile), (unsigned)((p.rows + kTile - 1) / kTile));
+}
+static inline dim3 iter_grid(const srt3d_params& p) {
+    return dim3((unsigned)((p.cols + kIterTX - 1) / kIterTX), (unsigned)((p.rows + kIterTY - 1) / kIterTY));
 }
 
 struct InitGrid {
@@ -1033,12 +1041,12 @@ hipError_t launch_iteration(const srt3d_params& p, const float* z, const int32_t
                             int dst, bool ds_next, hipStream_t s) {
     const IterArgs A = make_args(p);
     if (ds_next) {
-        SRT3D_BY_KR(p.K_max, p.R, hipLaunchKernelGGL((iteration_kernel<KK, RR, true>), tile_grid(p),
+        SRT3D_BY_KR(p.K_max, p.R, hipLaunchKernelGGL((iteration_kernel<KK, RR, true>), iter_grid(p),
                                                      dim3(kIterThreads), 0, s, A, z, n, st.hhat, st.scal, st.t[src],
                                                      st.alpha[src], st.active[src], st.t[dst], st.alpha[dst],
                                                      st.active[dst]));
     } else {
-        SRT3D_BY_KR(p.K_max, p.R, hipLaunchKernelGGL((iteration_kernel<KK, RR, false>), tile_grid(p),
+        SRT3D_BY_KR(p.K_max, p.R, hipLaunchKernelGGL((iteration_kernel<KK, RR, false>), iter_grid(p),
                                                      dim3(kIterThreads), 0, s, A, z, n, st.hhat, st.scal, st.t[src],
                                                      st.alpha[src], st.active[src], st.t[dst], st.alpha[dst],
                                                      st.active[dst]));
