@@ -33,6 +33,15 @@ __device__ __forceinline__ int32_t fold_stamp(int32_t x, int32_t T) {
 
 __device__ __forceinline__ float shfl_xor_f(float v, int mask) { return __shfl_xor(v, mask, kWave); }
 
+// Workgroup barrier ordering on-chip memory only: LDS traffic is complete and visible across it,
+// while global loads issued earlier stay in flight.  For kernels whose threads share data only
+// through LDS (global inputs read-only, each global output written by one thread).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Launch wrappers (defined in the .hip files).  All return hipSuccess or the launch error.
 hipError_t launch_phase_table(int T, float2* table, hipStream_t s);
 hipError_t launch_phase_indices(const int32_t* x, int64_t N, int T, int m, int32_t* k, hipStream_t s);

@@ -404,11 +404,28 @@ __global__ __launch_bounds__(256) void step_sizes_kernel(const int* __restrict__
 // and keeps a phasor recurrence re-anchored at the start of its slice and every 8 harmonics.
 // Partial gradient sums are combined over the four lanes, which then apply identical updates.
 constexpr int kLanesPerPixel = 4;
+constexpr int kMaxSlice = (SRT3D_MAX_M_RECON + kLanesPerPixel - 1) / kLanesPerPixel;   // harmonics per lane
 
-template <int K>
-__device__ __forceinline__ void residual_pass(const float2* __restrict__ zp, const float2* __restrict__ hp, int lo,
-                                              int hi, int T, float invT, float twoinvT, const float* tk,
-                                              const float* ak, const bool* on, float* gsum, bool depth) {
+// Where a lane's sketch values come from: the pixel's row in global memory, or registers filled
+// earlier (the fused iteration prefetches them at its start).  Same values either way.
+struct GlobalSketch {
+    const float2* zp;    // the pixel's sketch row
+    const float2* hp;    // the IRF spectrum
+    __device__ __forceinline__ float2 z(int l0, int) const { return zp[l0]; }
+    __device__ __forceinline__ float2 h(int l0) const { return hp[l0]; }
+};
+template <int MS>
+struct RegSketch {
+    const float2* zr;    // zr[j] = z_{lo + j + 1}, j < hi - lo <= MS (registers after inlining)
+    const float2* hs;    // the IRF spectrum in LDS
+    __device__ __forceinline__ float2 z(int, int j) const { return zr[j]; }
+    __device__ __forceinline__ float2 h(int l0) const { return hs[l0]; }
+};
+
+template <int K, int MS, class Src>
+__device__ __forceinline__ void residual_pass(const Src& src, int lo, int hi, int T, float invT, float twoinvT,
+                                              const float* tk, const float* ak, const bool* on, float* gsum,
+                                              bool depth) {
     // each lane anchors at the first harmonic of its slice; lane 0 of the pixel's group holds
     // harmonic 1, whose phasor drives everyone's recurrence
     const int base = (threadIdx.x & 63) & ~(kLanesPerPixel - 1);
@@ -420,10 +437,15 @@ __device__ __forceinline__ void residual_pass(const float2* __restrict__ zp, con
         u1[k].y = __shfl(u[k].y, base, 64);
     }
     const float w1 = 6.283185307179586f * invT;
-    for (int l0 = lo; l0 < hi; ++l0) {           // harmonic l = l0 + 1
+    // harmonic l = l0 + 1, l0 = lo + j; MS bounds the slice at compile time so that a register
+    // source is indexed by constants
+#pragma unroll
+    for (int j = 0; j < MS; ++j) {
+        const int l0 = lo + j;
+        if (l0 >= hi) break;
         const int l = l0 + 1;
-        const float2 h = hp[l0];
-        const float2 zl = zp[l0];
+        const float2 h = src.h(l0);
+        const float2 zl = src.z(l0, j);
         float2 g[K];
         float2 e = make_float2(-zl.x, -zl.y);
 #pragma unroll
@@ -452,26 +474,24 @@ __device__ __forceinline__ void residual_pass(const float2* __restrict__ zp, con
     }
 }
 
-// One data step for the K points of a pixel, by the four lanes `sub` = 0..3 of the pixel.
-template <int K>
-__device__ __forceinline__ void data_point(const float* __restrict__ z, const float* __restrict__ hhat, int pix,
-                                           int sub, int m, int T, float nn, float gam_t, float gam_a, float* tk,
-                                           float* ak, const bool* on) {
+// One data step for the K points of a pixel, by the four lanes `sub` = 0..3 of the pixel; each
+// lane's slice of harmonics has at most MS entries.
+template <int K, int MS, class Src>
+__device__ __forceinline__ void data_point(const Src& src, int sub, int m, int T, float nn, float gam_t, float gam_a,
+                                           float* tk, float* ak, const bool* on) {
     const int lo = (sub * m) / kLanesPerPixel, hi = ((sub + 1) * m) / kLanesPerPixel;
     const float Tf = (float)T, invT = 1.0f / Tf, twoinvT = 2.0f / Tf;
-    const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m);
-    const float2* hp = reinterpret_cast<const float2*>(hhat);
     float gt[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) gt[k] = 0.f;
-    residual_pass<K>(zp, hp, lo, hi, T, invT, twoinvT, tk, ak, on, gt, true);
+    residual_pass<K, MS>(src, lo, hi, T, invT, twoinvT, tk, ak, on, gt, true);
 #pragma unroll
     for (int k = 0; k < K; ++k)
         if (on[k]) tk[k] = wrap_t(tk[k] - gam_t * (-2.f * nn * ak[k] * gt[k]), Tf);
     float ga[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) ga[k] = 0.f;
-    residual_pass<K>(zp, hp, lo, hi, T, invT, twoinvT, tk, ak, on, ga, false);
+    residual_pass<K, MS>(src, lo, hi, T, invT, twoinvT, tk, ak, on, ga, false);
 #pragma unroll
     for (int k = 0; k < K; ++k)
         if (on[k]) ak[k] = ak[k] - gam_a * (2.f * nn * ga[k]);
@@ -499,7 +519,9 @@ __global__ __launch_bounds__(256) void data_step_kernel(IterArgs A, const float*
         any |= on[k];
     }
     if (!any) return;
-    data_point<K>(z, hhat, pix, sub, A.m, A.T, (float)n[pix], scal[1], scal[2], tk, ak, on);
+    const GlobalSketch src{reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * A.m),
+                           reinterpret_cast<const float2*>(hhat)};
+    data_point<K, kMaxSlice>(src, sub, A.m, A.T, (float)n[pix], scal[1], scal[2], tk, ak, on);
     if (sub != 0) return;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -764,6 +786,8 @@ constexpr int kIterTY = 8, kIterTX = 16;
 constexpr int kIterPix = kIterTY * kIterTX;
 constexpr int kIterThreads = kIterPix * kLanesPerPixel;
 
+constexpr int kPrefetchSlice = 8;   // the fused data step prefetches slices of up to 8 harmonics (m <= 32)
+
 template <int K, int R, bool DS_NEXT>
 __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
     IterArgs A, const float* __restrict__ z, const int32_t* __restrict__ n, const float* __restrict__ hhat,
@@ -779,10 +803,32 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
     __shared__ uint8_t s_a1[E1Y * E1 * K];
     __shared__ float s_oa[kIterPix * K];
     __shared__ uint8_t s_oo[kIterPix * K];
+    __shared__ float2 s_h[SRT3D_MAX_M_RECON];
     const int i0 = blockIdx.y * kIterTY, j0 = blockIdx.x * kIterTX;
+    // The data step's sketch slice (this thread's pixel and harmonics) is loaded first, into
+    // registers, and stays in flight through the denoisers: the barriers below order LDS only.
+    const int sub = threadIdx.x % kLanesPerPixel, pl = threadIdx.x / kLanesPerPixel;   // pl < kIterPix
+    const int dti = pl / kIterTX, dtj = pl % kIterTX;
+    const int dpi = i0 + dti, dpj = j0 + dtj;
+    const bool dpix_in = dpi < A.rows && dpj < A.cols;
+    const int dpix = dpix_in ? dpi * A.cols + dpj : 0;
+    // (one point per pixel only: with K = 2, 3 the slice's registers would cost the kernel its
+    // second block per CU, which is worth more than the hidden latency)
+    const bool prefetch = DS_NEXT && K == 1 && A.m <= kLanesPerPixel * kPrefetchSlice;
+    float2 zr[kPrefetchSlice];
+    if constexpr (DS_NEXT && K == 1) {
+        if (prefetch) {
+            const int lo = (sub * A.m) / kLanesPerPixel, hi = ((sub + 1) * A.m) / kLanesPerPixel;
+            const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)dpix * 2 * A.m);
+#pragma unroll
+            for (int j = 0; j < kPrefetchSlice; ++j) zr[j] = zp[lo + j < hi ? lo + j : lo];
+        }
+    }
+    if constexpr (DS_NEXT)
+        for (int l = threadIdx.x; l < A.m; l += blockDim.x) s_h[l] = reinterpret_cast<const float2*>(hhat)[l];
     load_region<K, false>(s_t2, s_a2, nullptr, E2Y, E2, i0 - 2 * R, j0 - 2 * R, A, t_in, a_in, act_in, nullptr);
     load_region<K, true>(s_td, s_a1, s_r1, E1Y, E1, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
-    __syncthreads();
+    lds_barrier();
     const float Tf = (float)A.T, invT = 1.0f / Tf, tau_z = scal[3];
     // depth denoiser on the tile + R ring
     for (int idx = threadIdx.x; idx < E1Y * E1 * K; idx += blockDim.x) {
@@ -792,7 +838,7 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
         if (s_a2[c2]) s_td[idx] = dd_point<K, R>(s_t2, s_a2, E2, ci, cj, k, Tf, invT, tau_z, A.lambda_z);
         else s_td[idx] = s_t2[c2];
     }
-    __syncthreads();
+    lds_barrier();
     // intensity denoiser on the tile (one thread per pixel)
     if (threadIdx.x < kIterPix) {
         const int ti = threadIdx.x / kIterTX, tj = threadIdx.x % kIterTX;
@@ -822,13 +868,11 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
         }
     }
     if constexpr (DS_NEXT) {
-        __syncthreads();
+        lds_barrier();
         // next data step, four lanes per pixel
-        const int sub = threadIdx.x % kLanesPerPixel, pl = threadIdx.x / kLanesPerPixel;   // pl < kIterPix
-        const int ti = pl / kIterTX, tj = pl % kIterTX;
-        const int pi = i0 + ti, pj = j0 + tj;
-        if (pi < A.rows && pj < A.cols) {
-            const int pix = pi * A.cols + pj;
+        const int ti = dti, tj = dtj;
+        if (dpix_in) {
+            const int pix = dpix;
             float tk[K], ak[K];
             bool on[K], any = false;
 #pragma unroll
@@ -838,7 +882,21 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
                 on[k] = s_oo[pl * K + k] != 0;
                 any |= on[k];
             }
-            if (any) data_point<K>(z, hhat, pix, sub, A.m, A.T, (float)n[pix], scal[1], scal[2], tk, ak, on);
+            if (any) {
+                if constexpr (K == 1) {
+                    if (prefetch) {
+                        const RegSketch<kPrefetchSlice> src{zr, s_h};
+                        data_point<K, kPrefetchSlice>(src, sub, A.m, A.T, (float)n[pix], scal[1], scal[2], tk, ak,
+                                                      on);
+                    } else {
+                        const GlobalSketch src{reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * A.m), s_h};
+                        data_point<K, kMaxSlice>(src, sub, A.m, A.T, (float)n[pix], scal[1], scal[2], tk, ak, on);
+                    }
+                } else {
+                    const GlobalSketch src{reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * A.m), s_h};
+                    data_point<K, kMaxSlice>(src, sub, A.m, A.T, (float)n[pix], scal[1], scal[2], tk, ak, on);
+                }
+            }
             if (sub == 0) {
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
