@@ -657,27 +657,52 @@ __device__ __forceinline__ float dd_point(const float* st, const uint8_t* sa, in
 }
 
 // Intensity denoiser: gated weighted mean of r = n * alpha around point k of cell (ci, cj).
+// The window's cells w = (di + R)(2R + 1) + (dj + R) are split into kIdParts interleaved parts
+// (w = s, s + 4, ...): part s is summed in window order, and the mean is
+// ((num_0 + num_1) + (num_2 + num_3)) / ((den_0 + den_1) + (den_2 + den_3)).  The fused iteration
+// gives each part to one of a pixel's four lanes and adds them with two butterfly shuffles (which
+// produce exactly that grouping in every lane); the stand-alone kernel adds the same parts in
+// one thread, so both compute the same bits.
+constexpr int kIdParts = 4;
+
 template <int K, int R>
-__device__ __forceinline__ float id_mean(const float* st, const uint8_t* sa, const float* sr, int E, int ci, int cj,
-                                         int k, float Tf, float invT, float tau_z) {
+__device__ __forceinline__ void id_part(const float* st, const uint8_t* sa, const float* sr, int E, int ci, int cj,
+                                        int k, float Tf, float invT, float tau_z, int s, float& num, float& den) {
+    constexpr int W = 2 * R + 1;
     const float tq = st[(ci * E + cj) * K + k];
-    float num = 0.f, den = 0.f;
+    num = 0.f;
+    den = 0.f;
 #pragma unroll
-    for (int di = -R; di <= R; ++di) {
-#pragma unroll
-        for (int dj = -R; dj <= R; ++dj) {
-            const float w = win_q<R>(di, dj);
+    for (int jj = 0; jj < (W * W + kIdParts - 1) / kIdParts; ++jj) {
+        const int w = s + kIdParts * jj;
+        if (w < W * W) {
+            const int di = w / W - R, dj = w % W - R;
+            const int u = (R + 1) * (R + 1) - di * di - dj * dj;
+            const float q = (float)(u * u * u * u);          // the integer window weight (exact)
 #pragma unroll
             for (int kk = 0; kk < K; ++kk) {
                 const int cn = ((ci + di) * E + (cj + dj)) * K + kk;
                 const float d = circ_diff(st[cn] - tq, Tf, invT);
-                const float gw = (sa[cn] && fabsf(d) <= tau_z) ? w : 0.f;
+                const float gw = (sa[cn] && fabsf(d) <= tau_z) ? q : 0.f;
                 num = fmaf(gw, sr[cn], num);
                 den += gw;
             }
         }
     }
+}
+
+__device__ __forceinline__ float id_ratio(float num, float den) {
     return num * __builtin_amdgcn_rcpf(den > 0.f ? den : 1.f);
+}
+
+// The whole mean in one thread (the four parts, added in the grouping above).
+template <int K, int R>
+__device__ __forceinline__ float id_mean(const float* st, const uint8_t* sa, const float* sr, int E, int ci, int cj,
+                                         int k, float Tf, float invT, float tau_z) {
+    float nm[kIdParts], dn[kIdParts];
+#pragma unroll
+    for (int s = 0; s < kIdParts; ++s) id_part<K, R>(st, sa, sr, E, ci, cj, k, Tf, invT, tau_z, s, nm[s], dn[s]);
+    return id_ratio((nm[0] + nm[1]) + (nm[2] + nm[3]), (dn[0] + dn[1]) + (dn[2] + dn[3]));
 }
 
 // New alpha and activity of a pixel's K points from their gated means rt (eq. 1 projection).
@@ -801,8 +826,6 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
     __shared__ float s_td[E1Y * E1 * K];         // depths after the depth denoiser, tile + R ring
     __shared__ float s_r1[E1Y * E1 * K];         // n * alpha after the data step
     __shared__ uint8_t s_a1[E1Y * E1 * K];
-    __shared__ float s_oa[kIterPix * K];
-    __shared__ uint8_t s_oo[kIterPix * K];
     __shared__ float2 s_h[SRT3D_MAX_M_RECON];
     const int i0 = blockIdx.y * kIterTY, j0 = blockIdx.x * kIterTX;
     // The data step's sketch slice (this thread's pixel and harmonics) is loaded first, into
@@ -839,72 +862,55 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
         else s_td[idx] = s_t2[c2];
     }
     lds_barrier();
-    // intensity denoiser on the tile (one thread per pixel)
-    if (threadIdx.x < kIterPix) {
-        const int ti = threadIdx.x / kIterTX, tj = threadIdx.x % kIterTX;
-        const int i = i0 + ti, j = j0 + tj;
-        if (i < A.rows && j < A.cols) {
-            float rt[K], an[K];
-            bool was[K], keep[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int c = ((ti + R) * E1 + (tj + R)) * K + k;
-                was[k] = s_a1[c] != 0;
-                rt[k] = was[k] ? id_mean<K, R>(s_td, s_a1, s_r1, E1, ti + R, tj + R, k, Tf, invT, tau_z) : 0.f;
-            }
-            id_update<K>(rt, was, (float)n[i * A.cols + j], A.r_min, an, keep);
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int o = threadIdx.x * K + k;
-                s_oa[o] = an[k];
-                s_oo[o] = keep[k] ? 1 : 0;
-                if constexpr (!DS_NEXT) {
-                    const int64_t q = ((int64_t)i * A.cols + j) * K + k;
-                    t_out[q] = s_td[((ti + R) * E1 + (tj + R)) * K + k];
-                    a_out[q] = an[k];
-                    act_out[q] = keep[k] ? 1 : 0;
-                }
-            }
-        }
-    }
-    if constexpr (DS_NEXT) {
-        lds_barrier();
-        // next data step, four lanes per pixel
+    // intensity denoiser, four lanes per pixel (the data step's lanes): each lane sums one part
+    // of the window, two shuffles combine them, and every lane holds the pixel's new state
+    if (dpix_in) {                                   // the same for the four lanes of a pixel
         const int ti = dti, tj = dtj;
-        if (dpix_in) {
-            const int pix = dpix;
-            float tk[K], ak[K];
-            bool on[K], any = false;
+        const int pix = dpix;
+        float rt[K], ak[K], tk[K];
+        bool was[K], on[K];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                tk[k] = s_td[((ti + R) * E1 + (tj + R)) * K + k];
-                ak[k] = s_oa[pl * K + k];
-                on[k] = s_oo[pl * K + k] != 0;
-                any |= on[k];
-            }
+        for (int k = 0; k < K; ++k) {
+            const int c = ((ti + R) * E1 + (tj + R)) * K + k;
+            was[k] = s_a1[c] != 0;
+            tk[k] = s_td[c];
+            float nm, dn;
+            id_part<K, R>(s_td, s_a1, s_r1, E1, ti + R, tj + R, k, Tf, invT, tau_z, sub, nm, dn);
+            nm += __shfl_xor(nm, 1, 64);
+            dn += __shfl_xor(dn, 1, 64);
+            nm += __shfl_xor(nm, 2, 64);
+            dn += __shfl_xor(dn, 2, 64);
+            rt[k] = was[k] ? id_ratio(nm, dn) : 0.f;
+        }
+        const float nq = (float)n[pix];
+        id_update<K>(rt, was, nq, A.r_min, ak, on);
+        if constexpr (DS_NEXT) {
+            // next data step
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < K; ++k) any |= on[k];
             if (any) {
                 if constexpr (K == 1) {
                     if (prefetch) {
                         const RegSketch<kPrefetchSlice> src{zr, s_h};
-                        data_point<K, kPrefetchSlice>(src, sub, A.m, A.T, (float)n[pix], scal[1], scal[2], tk, ak,
-                                                      on);
+                        data_point<K, kPrefetchSlice>(src, sub, A.m, A.T, nq, scal[1], scal[2], tk, ak, on);
                     } else {
                         const GlobalSketch src{reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * A.m), s_h};
-                        data_point<K, kMaxSlice>(src, sub, A.m, A.T, (float)n[pix], scal[1], scal[2], tk, ak, on);
+                        data_point<K, kMaxSlice>(src, sub, A.m, A.T, nq, scal[1], scal[2], tk, ak, on);
                     }
                 } else {
                     const GlobalSketch src{reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * A.m), s_h};
-                    data_point<K, kMaxSlice>(src, sub, A.m, A.T, (float)n[pix], scal[1], scal[2], tk, ak, on);
+                    data_point<K, kMaxSlice>(src, sub, A.m, A.T, nq, scal[1], scal[2], tk, ak, on);
                 }
             }
-            if (sub == 0) {
+        }
+        if (sub == 0) {
 #pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const int64_t q = (int64_t)pix * K + k;
-                    t_out[q] = tk[k];
-                    a_out[q] = ak[k];
-                    act_out[q] = on[k] ? 1 : 0;
-                }
+            for (int k = 0; k < K; ++k) {
+                const int64_t q = (int64_t)pix * K + k;
+                t_out[q] = tk[k];
+                a_out[q] = ak[k];
+                act_out[q] = on[k] ? 1 : 0;
             }
         }
     }
