@@ -604,8 +604,11 @@ __device__ constexpr float full_moment(int r, int c) {
 // Depth denoiser for point k of the pixel at LDS cell (ci, cj); t and act are (E x E cells) x K
 // arrays whose window cells lie within the array.  Returns the new depth.  With one point per
 // pixel and R <= 2 the normal matrix is the full-window sum minus the (few) neighbours that fail
-// the gate -- exact, since all entries are integers below 2^24; otherwise it sums the gated
-// neighbours.  Entries whose factor is zero for a given offset are skipped at compile time.
+// the gate -- exact, since all entries are integers below 2^24.  With several points per pixel
+// the K candidates of a window cell share the cell's offsets, so each cell contributes
+// (gated count) x (its weighted monomials) to the matrix and q x (sum of its gated offsets) x
+// (monomials) to the right-hand side: one set of updates per cell instead of per candidate.
+// Entries whose factor is zero for a given offset are skipped at compile time.
 template <int K, int R>
 __device__ __forceinline__ float dd_point(const float* st, const uint8_t* sa, int E, int ci, int cj, int k, float Tf,
                                           float invT, float tau_z, float lambda_z) {
@@ -622,27 +625,29 @@ __device__ __forceinline__ float dd_point(const float* st, const uint8_t* sa, in
         for (int dj = -R; dj <= R; ++dj) {
             const float q = win_q<R>(di, dj);
             const int r2 = di * di + dj * dj;
+            // the cell's gated offsets: their sum and how many pass (or, with SUB, fail) the gate
+            float dsum = 0.f, cnt = 0.f;
 #pragma unroll
             for (int kk = 0; kk < K; ++kk) {
                 const int cn = ((ci + di) * E + (cj + dj)) * K + kk;
                 const float d = circ_diff(st[cn] - tq, Tf, invT);
                 const bool gate = sa[cn] && fabsf(d) <= tau_z;
-                const float qd = q * (gate ? d : 0.f);
-                b[0] += qd;
-                if (di != 0) b[1] += (float)di * qd;
-                if (dj != 0) b[2] += (float)dj * qd;
-                if (r2 != 0) b[3] += (float)r2 * qd;
-                if (SUB ? !gate : gate) {
-                    const float sq = SUB ? -q : q;
-                    M[0][0] += sq;
-                    if (di != 0) { M[0][1] += sq * di; M[1][1] += sq * (di * di); }
-                    if (dj != 0) { M[0][2] += sq * dj; M[2][2] += sq * (dj * dj); }
-                    if (di != 0 && dj != 0) M[1][2] += sq * (di * dj);
-                    if (r2 != 0) { M[0][3] += sq * r2; M[3][3] += sq * (r2 * r2); }
-                    if (di != 0 && r2 != 0) M[1][3] += sq * (di * r2);
-                    if (dj != 0 && r2 != 0) M[2][3] += sq * (dj * r2);
-                }
+                dsum += gate ? d : 0.f;
+                cnt += (SUB ? !gate : gate) ? 1.f : 0.f;
             }
+            const float qd = q * dsum;
+            b[0] += qd;
+            if (di != 0) b[1] += (float)di * qd;
+            if (dj != 0) b[2] += (float)dj * qd;
+            if (r2 != 0) b[3] += (float)r2 * qd;
+            const float sq = (SUB ? -q : q) * cnt;
+            M[0][0] += sq;
+            if (di != 0) { M[0][1] += sq * di; M[1][1] += sq * (di * di); }
+            if (dj != 0) { M[0][2] += sq * dj; M[2][2] += sq * (dj * dj); }
+            if (di != 0 && dj != 0) M[1][2] += sq * (di * dj);
+            if (r2 != 0) { M[0][3] += sq * r2; M[3][3] += sq * (r2 * r2); }
+            if (di != 0 && r2 != 0) M[1][3] += sq * (di * r2);
+            if (dj != 0 && r2 != 0) M[2][3] += sq * (dj * r2);
         }
     }
 #pragma unroll
