@@ -59,7 +59,7 @@ __device__ __forceinline__ v8h bytes_to_h8(uint32_t w0, uint32_t w1, v2h bias) {
 }
 
 __device__ __forceinline__ _Float16 split_hi(float v) { return (_Float16)v; }
-__device__ __forceinline__ _Float16 split_lo(float v) { return (_Float16)((v - (float)(_Float16)v) * 2048.0f); }
+__device__ __forceinline__ _Float16 split_lo(float v) { return (_Float16)(v - (float)(_Float16)v); }
 
 // Sum over the 64 lanes: inclusive scans within each row of 16 lanes (DPP row shifts, no LDS),
 // then the four row totals.
@@ -148,8 +148,6 @@ __device__ __forceinline__ void mfma_tile(const uint8_t* hist, const float2* s_w
     bsum = __builtin_amdgcn_sad_u8(w1.x, 0u, bsum);
     bsum = __builtin_amdgcn_sad_u8(w1.y, 0u, bsum);
     const v8h A0 = bytes_to_h8(w0.x, w0.y, bias), A1 = bytes_to_h8(w1.x, w1.y, bias);
-    const _Float16 sc = (_Float16)(1.0f / 2048.0f);
-    const v8h S0 = A0 * sc, S1 = A1 * sc;
     v4f acc[Q][2];
     const v4f zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -157,9 +155,9 @@ __device__ __forceinline__ void mfma_tile(const uint8_t* hist, const float2* s_w
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             acc[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, V.hi[0][q][p], zero, 0, 0, 0);
-            acc[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(S0, V.lo[0][q][p], acc[q][p], 0, 0, 0);
+            acc[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, V.lo[0][q][p], acc[q][p], 0, 0, 0);
             acc[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, V.hi[1][q][p], acc[q][p], 0, 0, 0);
-            acc[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(S1, V.lo[1][q][p], acc[q][p], 0, 0, 0);
+            acc[q][p] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, V.lo[1][q][p], acc[q][p], 0, 0, 0);
         }
     // output element i of a tile: row 4 g + i, column c
 #pragma unroll
@@ -205,9 +203,9 @@ __device__ __forceinline__ void hist_add(uint32_t* h32, int32_t x, int T, int& b
 
 // Power-of-two T: the fold is a mask (two's complement makes x & (T - 1) the mathematical
 // modulus for negative x too) and the bad-stamp count is a compare, so no branch per stamp.
-__device__ __forceinline__ void hist_add_pow2(uint32_t* h32, int32_t x, uint32_t tmask, int& bad) {
+__device__ __forceinline__ void hist_add_pow2(uint32_t* h32, int32_t x, uint32_t tmask, uint32_t& orv) {
     const uint32_t xu = (uint32_t)x;
-    bad += xu > tmask ? 1 : 0;
+    orv |= xu;                                   // any stamp outside [0, T) shows up as a bit above T - 1
     const uint32_t xf = xu & tmask;
     bin_add(h32, xf);
 }
@@ -371,13 +369,21 @@ __global__ __launch_bounds__(kBinThreads) void sketch_binned_kernel(
     const uint32_t tmask = (uint32_t)T - 1u;
     auto consume = [&](const int32_t* v, const Run& d) {
         const int len = (int)(d.c1 - d.c0);                   // <= C
-        if (pow2 && len == C) {                               // full run: no guards, no branches
+        if (pow2) {
+            uint32_t orv = 0;
+            if (len == C) {                                   // full run: no guards, no branches
 #pragma unroll
-            for (int u = 0; u < U; ++u) hist_add_pow2(h32, v[u], tmask, bad_stamps);
-        } else if (pow2) {
+                for (int u = 0; u < U; ++u) hist_add_pow2(h32, v[u], tmask, orv);
+            } else {
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (lane + u * kWave < len) hist_add_pow2(h32, v[u], tmask, bad_stamps);
+                for (int u = 0; u < U; ++u)
+                    if (lane + u * kWave < len) hist_add_pow2(h32, v[u], tmask, orv);
+            }
+            if (orv > tmask) {                                // rare: count this lane's folded stamps
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (lane + u * kWave < len && (uint32_t)v[u] > tmask) ++bad_stamps;
+            }
         } else {
 #pragma unroll
             for (int u = 0; u < U; ++u)
