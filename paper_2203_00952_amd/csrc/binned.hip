@@ -11,8 +11,8 @@
 //    that is detected exactly (the byte sum then falls short of n) and the pixel is redone in
 //    chunks of at most 255 photons, which cannot overflow.
 //  * G = H[J x 64] . V[64 x 2m] runs as v_mfma_f32_16x16x32_f16.  Counts <= 255 are exact in
-//    FP16; V is split as V = V1 + 2^-11 V2 with V1 = fp16(V), V2 = fp16(2^11 (V - V1)), each
-//    product accumulated in FP32 in its own tile, so G carries V to about 2^-22.
+//    FP16; V is split as V = V1 + V2 with V1 = fp16(V), V2 = fp16(V - V1), both products
+//    accumulated in FP32 in one chain, so G carries V to about 2^-22 (2^-25 absolute).
 //  * The twiddle sum over j is FP32 FMAs in the MFMA output layout, then a fixed-order sum
 //    over the lanes' row groups; z = S / n in FP64 as in the photon pass.
 // The per-photon cost is one LDS atomic; the per-pixel cost is T * 2m * 2 MFMA multiply-adds.
@@ -91,6 +91,13 @@ __device__ __forceinline__ void bin_add(uint32_t* h32, uint32_t x) {
     atomicAdd(&h32[word], 1u << ((x >> 1) & 24u));
 }
 
+// Eight histogram bytes, replaced by zeros (ds_wrxchg_rtn_b64).
+__device__ __forceinline__ uint2 take8(uint8_t* p) {
+    const uint64_t v = __hip_atomic_exchange(reinterpret_cast<uint64_t*>(p), (uint64_t)0, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+}
+
 // B operands: lane c = lane & 15 is column (harmonic l = 16 q + c + 1), g = lane >> 4 its
 // k group (bins r = 32 ks + 8 g .. + 7).
 template <int Q>
@@ -128,18 +135,19 @@ __device__ __forceinline__ void load_vfrags(VFrags<Q>& V, const float2* __restri
     }
 }
 
-// One M-tile (rows j = 16 mt .. 16 mt + 15) of the product, added into sre/sim.  The split
-// V = V1 + 2^-11 V2 runs in one accumulator: the V2 products use A scaled by 2^-11 (exact: the
-// entries are small integers).  The twiddle of row j = 16 mt + 4 g + i factors exactly as
+// One M-tile (rows j = 16 mt .. 16 mt + 15) of the product, added into sre/sim.  Both terms of
+// the split V = V1 + V2 multiply the same A in one accumulator (V2 = fp16(V - V1) is stored
+// unscaled: where it is subnormal its absolute error stays below 2^-25).  The twiddle of row j = 16 mt + 4 g + i factors exactly as
 // W_l[16 mt] * W_l[4 g + i]: the lane's four row twiddles W_l[4 g + i] stay in registers, the
 // tile's common factor W_l[16 mt] is one LDS read per lane and tile.
 template <int Q>
-__device__ __forceinline__ void mfma_tile(const uint8_t* hist, const float2* s_wm, const VFrags<Q>& V, int mt,
+__device__ __forceinline__ void mfma_tile(uint8_t* hist, const float2* s_wm, const VFrags<Q>& V, int mt,
                                           int lane, v2h bias, float* sre, float* sim, uint32_t& bsum) {
     const int c = lane & 15, g = lane >> 4;
-    const uint8_t* row = hist + (16 * mt + c) * kRowBins + 8 * g;
-    const uint2 w0 = *reinterpret_cast<const uint2*>(row);
-    const uint2 w1 = *reinterpret_cast<const uint2*>(row + 32);
+    // each histogram byte is read by exactly one lane of one tile: read it and leave zero behind
+    // in one LDS exchange, so the histogram is clear for the next pixel without a separate pass
+    uint8_t* row = hist + (16 * mt + c) * kRowBins + 8 * g;
+    const uint2 w0 = take8(row), w1 = take8(row + 32);
     float2 wm[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) wm[q] = s_wm[mt * (16 * Q) + 16 * q + c];
@@ -186,7 +194,7 @@ __device__ __forceinline__ void mfma_tile(const uint8_t* hist, const float2* s_w
 // needs every A element to be a real bin (T a multiple of 1024, no padding rows); otherwise
 // the caller passes dc = 0.
 template <int Q>
-__device__ __forceinline__ void mfma_tiles(const uint8_t* hist, const float2* s_wm, const VFrags<Q>& V, int MT,
+__device__ __forceinline__ void mfma_tiles(uint8_t* hist, const float2* s_wm, const VFrags<Q>& V, int MT,
                                            int lane, int dc, float* sre, float* sim, uint32_t& bsum) {
     const _Float16 bh = (_Float16)(float)(-1024 - dc);
     const v2h bias = {bh, bh};
@@ -311,8 +319,7 @@ __global__ __launch_bounds__(kBinThreads) void sketch_binned_kernel(
             // about the mean count per bin (any integer is exact; this one keeps the bins small)
             int dc = T % 1024 == 0 ? (int)((float)count * (1.0f / (float)T) + 0.5f) : 0;
             if (dc > kSafeChunk) dc = kSafeChunk;
-            mfma_tiles<Q>(hist, s_wm, V, MT, lane, dc, sre, sim, bsum);
-            zero_hist_wave(hist, hbytes, lane);               // after this wave's reads (LDS is in order)
+            mfma_tiles<Q>(hist, s_wm, V, MT, lane, dc, sre, sim, bsum);   // leaves the histogram zero
             if (count > kSafeChunk && (int64_t)wave_sum_u32(bsum) != count) {
                 // Some bin passed 255: redo the pixel in chunks that cannot overflow (rare).
 #pragma unroll
@@ -329,7 +336,6 @@ __global__ __launch_bounds__(kBinThreads) void sketch_binned_kernel(
                     }
                     uint32_t unused = 0;
                     mfma_tiles<Q>(hist, s_wm, V, MT, lane, 0, sre, sim, unused);
-                    zero_hist_wave(hist, hbytes, lane);
                 }
             }
         }
