@@ -840,11 +840,9 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
     const int dpi = i0 + dti, dpj = j0 + dtj;
     const bool dpix_in = dpi < A.rows && dpj < A.cols;
     const int dpix = dpix_in ? dpi * A.cols + dpj : 0;
-    // (one point per pixel only: with K = 2, 3 the slice's registers would cost the kernel its
-    // second block per CU, which is worth more than the hidden latency)
-    const bool prefetch = DS_NEXT && K == 1 && A.m <= kLanesPerPixel * kPrefetchSlice;
+    const bool prefetch = DS_NEXT && A.m <= kLanesPerPixel * kPrefetchSlice;
     float2 zr[kPrefetchSlice];
-    if constexpr (DS_NEXT && K == 1) {
+    if constexpr (DS_NEXT) {
         if (prefetch) {
             const int lo = (sub * A.m) / kLanesPerPixel, hi = ((sub + 1) * A.m) / kLanesPerPixel;
             const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)dpix * 2 * A.m);
@@ -895,14 +893,9 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
 #pragma unroll
             for (int k = 0; k < K; ++k) any |= on[k];
             if (any) {
-                if constexpr (K == 1) {
-                    if (prefetch) {
-                        const RegSketch<kPrefetchSlice> src{zr, s_h};
-                        data_point<K, kPrefetchSlice>(src, sub, A.m, A.T, nq, scal[1], scal[2], tk, ak, on);
-                    } else {
-                        const GlobalSketch src{reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * A.m), s_h};
-                        data_point<K, kMaxSlice>(src, sub, A.m, A.T, nq, scal[1], scal[2], tk, ak, on);
-                    }
+                if (prefetch) {
+                    const RegSketch<kPrefetchSlice> src{zr, s_h};
+                    data_point<K, kPrefetchSlice>(src, sub, A.m, A.T, nq, scal[1], scal[2], tk, ak, on);
                 } else {
                     const GlobalSketch src{reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * A.m), s_h};
                     data_point<K, kMaxSlice>(src, sub, A.m, A.T, nq, scal[1], scal[2], tk, ak, on);
