@@ -7,22 +7,25 @@
 //     V_l[r] = exp(i w_l r),       W_l[j] = exp(i w_l 64 j),
 // with both phases reduced exactly mod T and read from the FP32 phase table.  Per pixel:
 //  * H is built in LDS by integer atomics, four 8-bit bins to a 32-bit word (one ds_add per
-//    photon, no per-photon harmonic work).  A bin that passes 255 carries into its neighbour;
-//    that is detected exactly (the byte sum then falls short of n) and the pixel is redone in
-//    chunks of at most 255 photons, which cannot overflow.
+//    photon, no per-photon harmonic work).  A bin that passes 255 carries into its neighbour (or
+//    out of the word); then the bins no longer sum to n.  A pixel with more than 255 photons sums
+//    its bins (exactly, on the matrix cores) and, if the sum is off, is redone in chunks of at
+//    most 255 photons, which cannot overflow.
 //  * G = H[J x 64] . V[64 x 2m] runs as v_mfma_f32_16x16x32_f16.  Counts <= 255 are exact in
 //    FP16; V is split as V = V1 + V2 with V1 = fp16(V), V2 = fp16(V - V1), both products
 //    accumulated in FP32 in one chain, so G carries V to about 2^-22 (2^-25 absolute).
-//  * The twiddle sum over j is FP32 FMAs in the MFMA output layout, then a fixed-order sum
-//    over the lanes' row groups; z = S / n in FP64 as in the photon pass.
-// The per-photon cost is one LDS atomic; the per-pixel cost is T * 2m * 2 MFMA multiply-adds.
+//  * The twiddle sum over j is FP32 FMAs in the MFMA output layout, then a fixed-order sum over the
+//    lanes' row groups; z = S / n in FP64 as in the photon pass.
+// The per-photon cost is one LDS atomic and five integer instructions; the per-pixel cost is
+// T * 2m * 2 MFMA multiply-adds and the conversion of T bytes to FP16.
 //
 // Work layout: every wave owns a contiguous range of pixels (so one contiguous range of stamps)
 // and its own histogram in LDS, and works through its pixels without any workgroup barrier, so
 // the latencies of one wave's steps (loads, LDS round trips, MFMA chains) overlap the work of
-// the others.  Stamps stream in runs of U per lane; two register sets alternate so the next run
-// is always in flight, across pixel boundaries.  The twiddles W are shared by the workgroup's
-// four waves in LDS; the V fragments (B operands) stay in registers.
+// the others.  Stamps stream in runs of U per lane through bounds-checked buffer loads (one
+// descriptor per run, no per-load address arithmetic); two register sets alternate so the next
+// run is always in flight, across pixel boundaries.  The twiddles W are shared by the
+// workgroup's four waves in LDS; the V fragments (B operands) stay in registers.
 #include "common.hpp"
 
 namespace srt3d {
@@ -32,11 +35,42 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef _Float16 v2h __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
 constexpr int kBinThreads = 256;
 constexpr int kBinWaves = kBinThreads / kWave;
 constexpr int kRowBins = 64;            // r range: bins per histogram row
+// A row is 64 8-bit bins (64 bytes) and 16 bytes of padding, so consecutive rows start 20 banks
+// apart and the lanes that read 8 bytes at the same place of 16 consecutive rows (an A-operand
+// load) touch different banks.
+constexpr int kRowPitch = 80;
+constexpr int kTilePitch = 16 * kRowPitch;
 constexpr int kSafeChunk = 255;         // photons per chunk that cannot overflow an 8-bit bin
+constexpr int kRsrcFlags = 0x00020000;  // buffer descriptor word 3: raw 32-bit dwords
+
+__device__ __forceinline__ uint32_t lds_address(const void* p) {
+    return (uint32_t)(size_t)(__attribute__((address_space(3))) const uint8_t*)p;
+}
+
+// Byte layout of a 64-bin histogram row: bin r sits in word r & 15, byte r >> 4, so the ~20
+// consecutive bins under a surface's return land in different words (and banks) instead of
+// five shared words, and the lanes adding them rarely collide on one address; the byte at
+// position p of a row holds bin row_bin(p).  The contraction only needs every A element and its
+// B element to name the same bin, so the V fragments are built with the same permutation.
+__device__ __forceinline__ int row_bin(int p) { return 16 * (p & 3) + (p >> 2); }
+
+// Byte address of the 32-bit word that holds bin x (0 <= x < 64 J) in the histogram at hbase (a
+// multiple of 64): row x >> 6 starts at byte 80 (x >> 6).
+__device__ __forceinline__ uint32_t bin_word(uint32_t hbase, uint32_t x) {
+    return __builtin_amdgcn_ubfe(x, 6, 16) * (uint32_t)kRowPitch + (((x & 15u) << 2) | hbase);
+}
+
+// 1 in the byte of its word that holds bin x.
+__device__ __forceinline__ uint32_t bin_one(uint32_t x) { return 1u << ((x >> 1) & 24u); }
+
+__device__ __forceinline__ void bin_add(uint32_t hbase, uint32_t x, uint32_t one) {
+    __hip_atomic_fetch_add((lds_u32*)(size_t)bin_word(hbase, x), one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 // Eight 8-bit counts (two words) as eight FP16 values b - c: each byte b becomes the FP16 bit
 // pattern 0x6400 | b, which is 1024 + b, and bias = -(1024 + c) is then added exactly.
@@ -58,6 +92,13 @@ __device__ __forceinline__ v8h bytes_to_h8(uint32_t w0, uint32_t w1, v2h bias) {
     return out;
 }
 
+// Eight histogram bytes, replaced by zeros (ds_wrxchg_rtn_b64).
+__device__ __forceinline__ uint2 take8(uint8_t* p) {
+    const uint64_t v = __hip_atomic_exchange(reinterpret_cast<uint64_t*>(p), (uint64_t)0, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+}
+
 __device__ __forceinline__ _Float16 split_hi(float v) { return (_Float16)v; }
 __device__ __forceinline__ _Float16 split_lo(float v) { return (_Float16)(v - (float)(_Float16)v); }
 
@@ -76,26 +117,6 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
     return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-// Byte layout of a 64-bin histogram row: bin r sits in word r & 15, byte r >> 4, so the ~20
-// consecutive bins under a surface's return land in different words (and banks) instead of
-// five shared words; the byte at position p of a row holds bin row_bin(p).  The contraction
-// only needs every A element and its B element to name the same bin, so the V fragments are
-// built with the same permutation.
-__device__ __forceinline__ int row_bin(int p) { return 16 * (p & 3) + (p >> 2); }
-
-__device__ __forceinline__ void bin_add(uint32_t* h32, uint32_t x) {
-    // byte address (x & ~63) + 4 (x & 15) + (x >> 4 & 3): word (x & ~63) / 4 + (x & 15)
-    const uint32_t word = __builtin_amdgcn_ubfe(x, 0, 4) | ((x >> 2) & ~15u);
-    atomicAdd(&h32[word], 1u << ((x >> 1) & 24u));
-}
-
-// Eight histogram bytes, replaced by zeros (ds_wrxchg_rtn_b64).
-__device__ __forceinline__ uint2 take8(uint8_t* p) {
-    const uint64_t v = __hip_atomic_exchange(reinterpret_cast<uint64_t*>(p), (uint64_t)0, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_WORKGROUP);
-    return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
 }
 
 // B operands: lane c = lane & 15 is column (harmonic l = 16 q + c + 1), g = lane >> 4 its
@@ -137,16 +158,18 @@ __device__ __forceinline__ void load_vfrags(VFrags<Q>& V, const float2* __restri
 
 // One M-tile (rows j = 16 mt .. 16 mt + 15) of the product, added into sre/sim.  Both terms of
 // the split V = V1 + V2 multiply the same A in one accumulator (V2 = fp16(V - V1) is stored
-// unscaled: where it is subnormal its absolute error stays below 2^-25).  The twiddle of row j = 16 mt + 4 g + i factors exactly as
-// W_l[16 mt] * W_l[4 g + i]: the lane's four row twiddles W_l[4 g + i] stay in registers, the
-// tile's common factor W_l[16 mt] is one LDS read per lane and tile.
+// unscaled: where it is subnormal its absolute error stays below 2^-25).  The twiddle of row
+// j = 16 mt + 4 g + i factors exactly as W_l[16 mt] * W_l[4 g + i]: the lane's four row twiddles
+// W_l[4 g + i] stay in registers, the tile's common factor W_l[16 mt] is one LDS read per lane
+// and tile.  The counts enter as count - dc (see mfma_tiles); their raw byte sum is added to bsum.
 template <int Q>
 __device__ __forceinline__ void mfma_tile(uint8_t* hist, const float2* s_wm, const VFrags<Q>& V, int mt,
                                           int lane, v2h bias, float* sre, float* sim, uint32_t& bsum) {
     const int c = lane & 15, g = lane >> 4;
-    // each histogram byte is read by exactly one lane of one tile: read it and leave zero behind
-    // in one LDS exchange, so the histogram is clear for the next pixel without a separate pass
-    uint8_t* row = hist + (16 * mt + c) * kRowBins + 8 * g;
+    // row c of the tile, bytes 8 g .. 8 g + 7 (k-step 0) and 32 + 8 g .. (k-step 1); each byte is
+    // read by exactly one lane of one tile: read it and leave zero behind in one LDS exchange, so
+    // the histogram is clear for the next pixel without a separate pass
+    uint8_t* row = hist + mt * kTilePitch + c * kRowPitch + 8 * g;
     const uint2 w0 = take8(row), w1 = take8(row + 32);
     float2 wm[Q];
 #pragma unroll
@@ -185,7 +208,7 @@ __device__ __forceinline__ void mfma_tile(uint8_t* hist, const float2* s_wm, con
 
 // Add the contribution of the histogram minus a constant `dc` in every bin to the lane's partial
 // sums sre/sim (harmonic 16 q + c + 1, summed over the lane's rows 16 mt + 4 g + i) and the
-// lane's raw byte sum to bsum.
+// lane's raw byte sum to bsum, and leave the histogram zero.
 //
 // The constant changes nothing exactly: the sum of exp(i w_l t) over all T bins is zero for
 // 0 < l < T.  With dc near the mean count it removes the common level of the bins, which would
@@ -193,29 +216,14 @@ __device__ __forceinline__ void mfma_tile(uint8_t* hist, const float2* s_wm, con
 // and the sum over j a cancellation whose FP32 rounding grows like n instead of sqrt(n).  It
 // needs every A element to be a real bin (T a multiple of 1024, no padding rows); otherwise
 // the caller passes dc = 0.
-template <int Q>
+template <int Q, int MTT>
 __device__ __forceinline__ void mfma_tiles(uint8_t* hist, const float2* s_wm, const VFrags<Q>& V, int MT,
                                            int lane, int dc, float* sre, float* sim, uint32_t& bsum) {
     const _Float16 bh = (_Float16)(float)(-1024 - dc);
     const v2h bias = {bh, bh};
-    for (int mt = 0; mt < MT; ++mt) mfma_tile<Q>(hist, s_wm, V, mt, lane, bias, sre, sim, bsum);
-}
-
-__device__ __forceinline__ void hist_add(uint32_t* h32, int32_t x, int T, int& bad) {
-    if ((uint32_t)x >= (uint32_t)T) {
-        ++bad;
-        x = fold_stamp(x, T);
-    }
-    bin_add(h32, (uint32_t)x);
-}
-
-// Power-of-two T: the fold is a mask (two's complement makes x & (T - 1) the mathematical
-// modulus for negative x too) and the bad-stamp count is a compare, so no branch per stamp.
-__device__ __forceinline__ void hist_add_pow2(uint32_t* h32, int32_t x, uint32_t tmask, uint32_t& orv) {
-    const uint32_t xu = (uint32_t)x;
-    orv |= xu;                                   // any stamp outside [0, T) shows up as a bit above T - 1
-    const uint32_t xf = xu & tmask;
-    bin_add(h32, xf);
+#pragma unroll
+    for (int mt = 0; mt < MTT; ++mt)
+        if (mt < MT) mfma_tile<Q>(hist, s_wm, V, mt, lane, bias, sre, sim, bsum);
 }
 
 __device__ __forceinline__ void zero_hist_wave(uint8_t* hist, int bytes, int lane) {
@@ -232,31 +240,29 @@ struct Run {
 };
 
 template <int Q, int MTT, int U>
-__global__ __launch_bounds__(kBinThreads) void sketch_binned_kernel(
+__global__ __launch_bounds__(kBinThreads) __attribute__((amdgpu_waves_per_eu(Q == 1 && MTT == 4 && U <= 8 ? 4 : 1))) void sketch_binned_kernel(
     const int32_t* __restrict__ stamps, int64_t N, const int64_t* __restrict__ offsets, int P, int T, int m,
     const float2* __restrict__ table, float* __restrict__ z, int32_t* __restrict__ nout, double* __restrict__ acc,
     int64_t* __restrict__ nacc, int32_t* __restrict__ err) {
-    constexpr int HB = MTT * 16 * kRowBins;                   // histogram bytes per wave
+    constexpr int HB = MTT * kTilePitch;                      // histogram bytes per wave
     constexpr int C = U * kWave;                              // stamps per run
-    __shared__ __align__(16) uint8_t s_hist[kBinWaves][HB];
+    __shared__ __align__(64) uint8_t s_hist[kBinWaves][HB];
     __shared__ float2 s_wm[MTT * 16 * Q];
-    __shared__ float2 s_red[kBinWaves][4][Q][16];
 
     // the wave index is uniform across the wave: say so, so that everything derived from it (the
     // pixel range, each run, the offsets loads) stays in scalar registers and scalar loads
     const int lane = threadIdx.x & (kWave - 1), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int J = (T + kRowBins - 1) / kRowBins;
     const int MT = (J + 15) / 16;
-    const int hbytes = MT * 16 * kRowBins;
     uint8_t* hist = s_hist[wave];
-    uint32_t* h32 = reinterpret_cast<uint32_t*>(hist);
+    const uint32_t hbase = lds_address(hist);
 
     // tile twiddle factors W_l[16 mt] (zero for l > m), shared by the waves
     for (int idx = threadIdx.x; idx < MT * 16 * Q; idx += kBinThreads) {
         const int mt = idx / (16 * Q), l = idx % (16 * Q) + 1;
         s_wm[idx] = l <= m ? table[(int)(((int64_t)l * 16 * kRowBins * mt) % T)] : make_float2(0.f, 0.f);
     }
-    zero_hist_wave(hist, hbytes, lane);
+    zero_hist_wave(hist, HB, lane);
     VFrags<Q> V;
     load_vfrags<Q>(V, table, T, m, lane);
     __syncthreads();                                          // s_wm complete; the only barrier
@@ -289,21 +295,16 @@ __global__ __launch_bounds__(kBinThreads) void sketch_binned_kernel(
         }
         return pixel_run(d.pix + 1, d.raw_e, uniform64(offsets[d.pix + 2]));
     };
-    // Every run issues its U loads, valid or not, with indices clamped into the stamp array: the
-    // compiler then knows exactly which loads are younger than a run's data and waits for that
-    // run alone.  Lanes past the run's end hold values that are never used.  With no stamps at
-    // all, `src` is a dummy readable address (the offsets array).
-    const int32_t* src = N > 0 ? stamps : reinterpret_cast<const int32_t*>(offsets);
-    const int64_t last = N > 0 ? N - 1 : 0;
+    // Every run issues its U loads, valid or not, through a buffer descriptor that covers exactly
+    // the run's stamps: loads past its end (a short or invalid run) return 0 without touching
+    // memory, and the compiler knows exactly which loads are younger than a run's data, so it
+    // waits for that run alone.
     auto issue = [&](int32_t* v, const Run& d) {
-        const int64_t base = d.c0 < last ? d.c0 : last;
-        const uint32_t lim = (uint32_t)(last - base < (int64_t)C ? last - base : (int64_t)C);
-        const int32_t* rp = src + base;
+        const int bytes = d.valid ? (int)(d.c1 - d.c0) * 4 : 0;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t*>(stamps) + d.c0, (short)0, bytes, kRsrcFlags);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t o = (uint32_t)(lane + u * kWave);
-            v[u] = rp[o < lim ? o : lim];
-        }
+        for (int u = 0; u < U; ++u) v[u] = __builtin_amdgcn_raw_buffer_load_b32(rs, (lane + u * kWave) * 4, 0, 0);
     };
 
     // All of pixel d.pix is in the histogram: contract, check, emit, clear.
@@ -315,54 +316,54 @@ __global__ __launch_bounds__(kBinThreads) void sketch_binned_kernel(
 #pragma unroll
         for (int q = 0; q < Q; ++q) sre[q] = sim[q] = 0.f;
         if (count > 0) {
-            uint32_t bsum = 0;
             // about the mean count per bin (any integer is exact; this one keeps the bins small)
             int dc = T % 1024 == 0 ? (int)((float)count * (1.0f / (float)T) + 0.5f) : 0;
             if (dc > kSafeChunk) dc = kSafeChunk;
-            mfma_tiles<Q>(hist, s_wm, V, MT, lane, dc, sre, sim, bsum);   // leaves the histogram zero
+            uint32_t bsum = 0;
+            mfma_tiles<Q, MTT>(hist, s_wm, V, MT, lane, dc, sre, sim, bsum);   // leaves the histogram zero
             if (count > kSafeChunk && (int64_t)wave_sum_u32(bsum) != count) {
-                // Some bin passed 255: redo the pixel in chunks that cannot overflow (rare).
+                // Some bin passed 255: redo the pixel in chunks that cannot (rare).
 #pragma unroll
                 for (int q = 0; q < Q; ++q) sre[q] = sim[q] = 0.f;
                 for (int64_t c0 = d.pb; c0 < d.pe; c0 += kSafeChunk) {
                     const int64_t ce = c0 + kSafeChunk < d.pe ? c0 + kSafeChunk : d.pe;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int64_t i = c0 + lane + (int64_t)u * kWave;
-                        if (i < ce) {
-                            int dummy = 0;
-                            hist_add(h32, stamps[i], T, dummy);   // folds were counted in the first pass
-                        }
+                    for (int64_t i = c0 + lane; i < ce; i += kWave) {
+                        int32_t x = stamps[i];
+                        if ((uint32_t)x >= (uint32_t)T) x = fold_stamp(x, T);   // counted in the first pass
+                        bin_add(hbase, (uint32_t)x, bin_one((uint32_t)x));
                     }
                     uint32_t unused = 0;
-                    mfma_tiles<Q>(hist, s_wm, V, MT, lane, 0, sre, sim, unused);
+                    mfma_tiles<Q, MTT>(hist, s_wm, V, MT, lane, 0, sre, sim, unused);
                 }
             }
         }
-        // sum over the four row groups g, fixed order
-        const int c = lane & 15, g = lane >> 4;
+        // sum over the four row groups g, fixed order ((g0 + g1) + (g2 + g3)) in every lane
 #pragma unroll
-        for (int q = 0; q < Q; ++q) s_red[wave][g][q][c] = make_float2(sre[q], sim[q]);
+        for (int q = 0; q < Q; ++q) {
+            sre[q] += __shfl_xor(sre[q], 16, kWave);
+            sim[q] += __shfl_xor(sim[q], 16, kWave);
+            sre[q] += __shfl_xor(sre[q], 32, kWave);
+            sim[q] += __shfl_xor(sim[q], 32, kWave);
+        }
         if (lane < 16 * Q) {
-            const int q = lane >> 4, l = 16 * q + c + 1;
-            if (l <= m) {
-                float s0 = 0.f, s1 = 0.f;
+            const int c = lane & 15, q = lane >> 4, l = 16 * q + c + 1;
+            float s0 = sre[0], s1 = sim[0];
 #pragma unroll
-                for (int gg = 0; gg < 4; ++gg) {
-                    const float2 v = s_red[wave][gg][q][c];
-                    s0 += v.x;
-                    s1 += v.y;
+            for (int qq = 1; qq < Q; ++qq)
+                if (q == qq) {
+                    s0 = sre[qq];
+                    s1 = sim[qq];
                 }
+            if (l <= m) {
                 const int64_t o = pix * m * 2 + 2 * (l - 1);
+                const double inv = count_total > 0 ? 1.0 / (double)count_total : 0.0;
                 if (acc) {
                     const double a0 = acc[o] + (double)s0, a1 = acc[o + 1] + (double)s1;
                     acc[o] = a0;
                     acc[o + 1] = a1;
-                    z[o] = count_total > 0 ? (float)(a0 / (double)count_total) : 0.f;
-                    z[o + 1] = count_total > 0 ? (float)(a1 / (double)count_total) : 0.f;
+                    *reinterpret_cast<float2*>(z + o) = make_float2((float)(a0 * inv), (float)(a1 * inv));
                 } else {
-                    z[o] = count > 0 ? (float)((double)s0 / (double)count) : 0.f;
-                    z[o + 1] = count > 0 ? (float)((double)s1 / (double)count) : 0.f;
+                    *reinterpret_cast<float2*>(z + o) = make_float2((float)((double)s0 * inv), (float)((double)s1 * inv));
                 }
             }
         }
@@ -371,29 +372,34 @@ __global__ __launch_bounds__(kBinThreads) void sketch_binned_kernel(
             nout[pix] = (int32_t)(count_total > 0x7fffffff ? 0x7fffffff : count_total);
         }
     };
-    const bool pow2 = (T & (T - 1)) == 0;
-    const uint32_t tmask = (uint32_t)T - 1u;
     auto consume = [&](const int32_t* v, const Run& d) {
         const int len = (int)(d.c1 - d.c0);                   // <= C
-        if (pow2) {
-            uint32_t orv = 0;
+        // loads past the run's end read 0, which is in range: the largest stamp (as unsigned, so
+        // negative ones count as large) decides whether this run needs the folding path
+        uint32_t mx = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) mx = max(mx, (uint32_t)v[u]);
+        if (__builtin_amdgcn_ballot_w64(mx >= (uint32_t)T) == 0) {
             if (len == C) {                                   // full run: no guards, no branches
 #pragma unroll
-                for (int u = 0; u < U; ++u) hist_add_pow2(h32, v[u], tmask, orv);
-            } else {
+                for (int u = 0; u < U; ++u) bin_add(hbase, (uint32_t)v[u], bin_one((uint32_t)v[u]));
+            } else {                                          // only the lanes inside the run add
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (lane + u * kWave < len) hist_add_pow2(h32, v[u], tmask, orv);
+                    if (lane + u * kWave < len) bin_add(hbase, (uint32_t)v[u], bin_one((uint32_t)v[u]));
             }
-            if (orv > tmask) {                                // rare: count this lane's folded stamps
+        } else {                                              // rare: stamps outside [0, T) are counted and folded
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (lane + u * kWave < len && (uint32_t)v[u] > tmask) ++bad_stamps;
+            for (int u = 0; u < U; ++u) {
+                if (lane + u * kWave < len) {
+                    int32_t x = v[u];
+                    if ((uint32_t)x >= (uint32_t)T) {
+                        ++bad_stamps;
+                        x = fold_stamp(x, T);
+                    }
+                    bin_add(hbase, (uint32_t)x, bin_one((uint32_t)x));
+                }
             }
-        } else {
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (lane + u * kWave < len) hist_add(h32, v[u], T, bad_stamps);
         }
         if (d.last) complete(d);
     };
