@@ -140,7 +140,9 @@ __device__ __forceinline__ void load_vfrags(VFrags<Q>& V, const float2* __restri
                 const int r = row_bin(32 * ks + 8 * g + e);
                 float cv = 0.f, sv = 0.f;
                 if (l <= m) {
-                    const float2 t = table[(l * r) % T];
+                    int ph = l * r;                         // < 32 * 64: a few subtractions at most for T >= 1024
+                    while (ph >= T) ph -= T;
+                    const float2 t = table[ph];
                     cv = t.x;
                     sv = t.y;
                 }
