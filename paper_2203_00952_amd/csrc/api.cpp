@@ -151,14 +151,15 @@ int srt3d_iterate(srt3d_state* st, const float* d_z, const int32_t* d_n, const s
     if ((rc = check_state(st)) != SRT3D_OK) return rc;
     if (!d_z || !d_n || iters < 0) return SRT3D_EINVAL;
     if (iters == 0) return SRT3D_OK;
-    // data step, then one fused launch per iteration: depth and intensity denoisers of
-    // iteration it and the data step of iteration it + 1 (none after the last)
+    // data step, then per iteration the depth and intensity denoisers of iteration it and the data
+    // step of iteration it + 1 (none after the last): one fused launch, or with several points per
+    // pixel a depth-denoiser launch and the fused rest
     hipStream_t s = as_stream(stream);
     if (launch_data_step(*p, d_z, d_n, *st, st->cur, s) != hipSuccess) return SRT3D_EDEVICE;
     for (int it = 0; it < iters; ++it) {
-        const int c = st->cur;
-        if (launch_iteration(*p, d_z, d_n, *st, c, 1 - c, it + 1 < iters, s) != hipSuccess) return SRT3D_EDEVICE;
-        st->cur = 1 - c;
+        int next = st->cur;
+        if (launch_iteration(*p, d_z, d_n, *st, st->cur, it + 1 < iters, s, &next) != hipSuccess) return SRT3D_EDEVICE;
+        st->cur = next;
     }
     return SRT3D_OK;
 }

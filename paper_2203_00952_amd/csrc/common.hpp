@@ -64,7 +64,7 @@ hipError_t launch_depth_denoise(const srt3d_params& p, const srt3d_state& st, in
 hipError_t launch_intensity_denoise(const srt3d_params& p, const int32_t* n, const srt3d_state& st, int src,
                                     int dst, hipStream_t s);
 hipError_t launch_iteration(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st, int src,
-                            int dst, bool ds_next, hipStream_t s);
+                            bool ds_next, hipStream_t s, int* out);   // *out: the buffer now holding the state
 hipError_t launch_finalize(const srt3d_params& p, const int32_t* n, const srt3d_state& st, float* depth,
                            float* intensity, uint8_t* active, float* bg, hipStream_t s);
 size_t init_ws_bytes(const srt3d_params& p);

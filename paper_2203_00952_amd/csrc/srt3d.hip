@@ -812,13 +812,18 @@ __global__ __launch_bounds__(kTile * kTile) void intensity_denoise_kernel(
 // instead of three; four threads per tile pixel so that the data step runs four lanes per pixel
 // in one round.  Tiles of 8 x 16 (512 threads) let two or more blocks share a CU, so one block's
 // load and barrier waits overlap another's denoiser arithmetic.
+//
+// DD_DONE: the input is the state after the depth denoiser (depth_denoise_kernel ran first), so
+// the tile skips its own depth fits.  With several points per pixel the fit dominates the
+// iteration and the ring makes each tile fit 1.9 times its own pixels; the separate launch fits
+// each pixel once.  dd_point sees the same inputs either way, so both forms give the same bits.
 constexpr int kIterTY = 8, kIterTX = 16;
 constexpr int kIterPix = kIterTY * kIterTX;
 constexpr int kIterThreads = kIterPix * kLanesPerPixel;
 
 constexpr int kPrefetchSlice = 8;   // the fused data step prefetches slices of up to 8 harmonics (m <= 32)
 
-template <int K, int R, bool DS_NEXT>
+template <int K, int R, bool DS_NEXT, bool DD_DONE>
 __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
     IterArgs A, const float* __restrict__ z, const int32_t* __restrict__ n, const float* __restrict__ hhat,
     const float* __restrict__ scal, const float* __restrict__ t_in, const float* __restrict__ a_in,
@@ -852,19 +857,22 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
     }
     if constexpr (DS_NEXT)
         for (int l = threadIdx.x; l < A.m; l += blockDim.x) s_h[l] = reinterpret_cast<const float2*>(hhat)[l];
-    load_region<K, false>(s_t2, s_a2, nullptr, E2Y, E2, i0 - 2 * R, j0 - 2 * R, A, t_in, a_in, act_in, nullptr);
+    if constexpr (!DD_DONE)
+        load_region<K, false>(s_t2, s_a2, nullptr, E2Y, E2, i0 - 2 * R, j0 - 2 * R, A, t_in, a_in, act_in, nullptr);
     load_region<K, true>(s_td, s_a1, s_r1, E1Y, E1, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
     lds_barrier();
     const float Tf = (float)A.T, invT = 1.0f / Tf, tau_z = scal[3];
-    // depth denoiser on the tile + R ring
-    for (int idx = threadIdx.x; idx < E1Y * E1 * K; idx += blockDim.x) {
-        const int k = idx % K, cell = idx / K;
-        const int ci = cell / E1 + R, cj = cell % E1 + R;          // cell in the E2 region
-        const int c2 = (ci * E2 + cj) * K + k;
-        if (s_a2[c2]) s_td[idx] = dd_point<K, R>(s_t2, s_a2, E2, ci, cj, k, Tf, invT, tau_z, A.lambda_z);
-        else s_td[idx] = s_t2[c2];
+    if constexpr (!DD_DONE) {
+        // depth denoiser on the tile + R ring
+        for (int idx = threadIdx.x; idx < E1Y * E1 * K; idx += blockDim.x) {
+            const int k = idx % K, cell = idx / K;
+            const int ci = cell / E1 + R, cj = cell % E1 + R;          // cell in the E2 region
+            const int c2 = (ci * E2 + cj) * K + k;
+            if (s_a2[c2]) s_td[idx] = dd_point<K, R>(s_t2, s_a2, E2, ci, cj, k, Tf, invT, tau_z, A.lambda_z);
+            else s_td[idx] = s_t2[c2];
+        }
+        lds_barrier();
     }
-    lds_barrier();
     // intensity denoiser, four lanes per pixel (the data step's lanes): each lane sums one part
     // of the window, two shuffles combine them, and every lane holds the pixel's new state
     if (dpix_in) {                                   // the same for the four lanes of a pixel
@@ -1099,20 +1107,32 @@ hipError_t launch_intensity_denoise(const srt3d_params& p, const int32_t* n, con
     return hipGetLastError();
 }
 
+// Whether an iteration runs as a depth-denoiser launch plus the fused rest (several points per
+// pixel: the fits dominate, and the fused kernel's ring would repeat them) or as one launch.
+static bool split_iteration(const srt3d_params& p) { return p.K_max >= 2; }
+
 hipError_t launch_iteration(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st, int src,
-                            int dst, bool ds_next, hipStream_t s) {
+                            bool ds_next, hipStream_t s, int* out) {
     const IterArgs A = make_args(p);
-    if (ds_next) {
-        SRT3D_BY_KR(p.K_max, p.R, hipLaunchKernelGGL((iteration_kernel<KK, RR, true>), iter_grid(p),
-                                                     dim3(kIterThreads), 0, s, A, z, n, st.hhat, st.scal, st.t[src],
-                                                     st.alpha[src], st.active[src], st.t[dst], st.alpha[dst],
-                                                     st.active[dst]));
-    } else {
-        SRT3D_BY_KR(p.K_max, p.R, hipLaunchKernelGGL((iteration_kernel<KK, RR, false>), iter_grid(p),
-                                                     dim3(kIterThreads), 0, s, A, z, n, st.hhat, st.scal, st.t[src],
-                                                     st.alpha[src], st.active[src], st.t[dst], st.alpha[dst],
-                                                     st.active[dst]));
+    const int dst = 1 - src;
+    int in = src, to = dst;
+    if (split_iteration(p)) {
+        hipError_t e = launch_depth_denoise(p, st, src, dst, s);      // src -> dst, each pixel fitted once
+        if (e != hipSuccess) return e;
+        in = dst;
+        to = src;
     }
+#define SRT3D_ITER(DS, DD)                                                                                          \
+    SRT3D_BY_KR(p.K_max, p.R, hipLaunchKernelGGL((iteration_kernel<KK, RR, DS, DD>), iter_grid(p), dim3(kIterThreads), \
+                                                 0, s, A, z, n, st.hhat, st.scal, st.t[in], st.alpha[in],            \
+                                                 st.active[in], st.t[to], st.alpha[to], st.active[to]))
+    const bool dd_done = in != src;
+    if (ds_next && dd_done) { SRT3D_ITER(true, true); }
+    else if (ds_next) { SRT3D_ITER(true, false); }
+    else if (dd_done) { SRT3D_ITER(false, true); }
+    else { SRT3D_ITER(false, false); }
+#undef SRT3D_ITER
+    *out = to;
     return hipGetLastError();
 }
 
