@@ -216,14 +216,44 @@ __global__ void init_grid_table_kernel(int T, int m, int stride, int G, int KS, 
     EB[idx] = (float)v;
 }
 
-template <int K, int KSMAX>
+// Correlation of the atom with itself at grid lag d (d = 0 .. G - 1, lag d * stride):
+// rho[d] = Re sum_l conj(hhat_l) hhat_l e^{-i w_l d stride} = sum_l |hhat_l|^2 cos(w_l d stride), even
+// in d.  Removing the atom a hhat_l e^{i w_l tau_k} from the working sketch lowers the grid
+// correlation at tau by exactly a rho(tau - tau_k), so the greedy picks after the first update
+// the correlation instead of recomputing it.  Exact integer phase, FP64 sum, stored as FP32.
+__global__ void init_rho_kernel(const float* __restrict__ hhat, int T, int m, int stride, int G, int GP,
+                                float* __restrict__ rho) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= GP) return;
+    double acc = 0.0;
+    if (d < G) {
+        const int64_t lag = ((int64_t)d * stride) % T;
+        for (int l = 1; l <= m; ++l) {
+            const double hr = hhat[2 * (l - 1)], hi = hhat[2 * (l - 1) + 1];
+            const int64_t ph = ((int64_t)l * lag) % T;
+            acc += (hr * hr + hi * hi) * cospi(2.0 * (double)ph / (double)T);
+        }
+    }
+    rho[d] = (float)acc;          // lags past the grid: 0 (read only with a zero amplitude)
+}
+
+// RHO: the first pick's correlation stays in LDS (NT <= KSMAX column tiles, 16 bytes per lane and
+// tile) and the later picks update it with rho; otherwise every pick recomputes it from the
+// updated working sketch.
+template <int K, int KSMAX, bool RHO>
 __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, const int32_t* __restrict__ n,
                                                    const float* __restrict__ hhat, const float* __restrict__ scal,
-                                                   const float* __restrict__ EB, int P, int T, int m, int stride,
-                                                   int G, int KS, int NT, float r_min, float* __restrict__ t_out,
-                                                   float* __restrict__ a_out, uint8_t* __restrict__ act_out,
-                                                   int* __restrict__ nmax_part) {
+                                                   const float* __restrict__ EB, const float* __restrict__ rho, int P,
+                                                   int T, int m, int stride, int G, int KS, int NT, float r_min,
+                                                   float* __restrict__ t_out, float* __restrict__ a_out,
+                                                   uint8_t* __restrict__ act_out, int* __restrict__ nmax_part) {
     __shared__ int s_nmax[4];
+    __shared__ float s_rho[RHO ? 16 * KSMAX : 1];
+    __shared__ v4f s_C[RHO ? 4 * KSMAX * 64 : 1];     // [wave][column tile][lane]
+    if constexpr (RHO) {
+        for (int i = threadIdx.x; i < 16 * KSMAX; i += blockDim.x) s_rho[i] = i < 16 * NT ? rho[i] : 0.f;
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r = lane & 15, kq = lane >> 4;          // A row (pixel) / k quarter of this lane
     const float e2 = scal[4], invT = 1.0f / (float)T, twoinvT = 2.0f / (float)T;
@@ -252,6 +282,8 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
         int tau_row[K][4];                              // picks of C rows 4 kq + i
         int tau_mine[K];                                // picks of A row r
         float amp_mine[K];
+        v4f* Cw = s_C + (RHO ? wv * KSMAX * 64 + lane : 0);   // RHO: this lane's correlation, tile nt at Cw[64 nt]
+        float amp_row[4] = {0.f, 0.f, 0.f, 0.f};       // RHO: the previous pick's amplitude per C row
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             float ya[KSMAX];
@@ -288,24 +320,44 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
                     }
                 }
             };
-            for (int nt = 0; nt < NT; nt += 2) {
-                const float* eb0 = EB + (int64_t)nt * KS * 64 + lane;
-                v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-                if (nt + 1 < NT) {
-                    const float* eb1 = eb0 + KS * 64;
+            if (RHO && k > 0) {
+                // remove the previous pick of each row: c(g) -= a rho(|g - g_prev|)
+                for (int nt = 0; nt < NT; ++nt) {
+                    v4f c = Cw[64 * nt];
+                    const int g = 16 * nt + r;
 #pragma unroll
-                    for (int ks = 0; ks < KSMAX; ++ks)
-                        if (ks < KS) {
-                            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[ks], eb0[ks * 64], acc0, 0, 0, 0);
-                            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[ks], eb1[ks * 64], acc1, 0, 0, 0);
+                    for (int i = 0; i < 4; ++i) {
+                        const int d = g - tau_row[k - 1][i] / stride;
+                        c[i] -= amp_row[i] * s_rho[d < 0 ? -d : d];
+                    }
+                    Cw[64 * nt] = c;
+                    scan(c, nt);
+                }
+            } else {
+                for (int nt = 0; nt < NT; nt += 2) {
+                    const float* eb0 = EB + (int64_t)nt * KS * 64 + lane;
+                    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+                    if (nt + 1 < NT) {
+                        const float* eb1 = eb0 + KS * 64;
+#pragma unroll
+                        for (int ks = 0; ks < KSMAX; ++ks)
+                            if (ks < KS) {
+                                acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[ks], eb0[ks * 64], acc0, 0, 0, 0);
+                                acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[ks], eb1[ks * 64], acc1, 0, 0, 0);
+                            }
+                        scan(acc0, nt);
+                        scan(acc1, nt + 1);
+                        if (RHO) {
+                            Cw[64 * nt] = acc0;
+                            Cw[64 * (nt + 1)] = acc1;
                         }
-                    scan(acc0, nt);
-                    scan(acc1, nt + 1);
-                } else {
+                    } else {
 #pragma unroll
-                    for (int ks = 0; ks < KSMAX; ++ks)
-                        if (ks < KS) acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[ks], eb0[ks * 64], acc0, 0, 0, 0);
-                    scan(acc0, nt);
+                        for (int ks = 0; ks < KSMAX; ++ks)
+                            if (ks < KS) acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[ks], eb0[ks * 64], acc0, 0, 0, 0);
+                        scan(acc0, nt);
+                        if (RHO) Cw[64 * nt] = acc0;
+                    }
                 }
             }
 #pragma unroll
@@ -326,6 +378,7 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
                 const bool none = bestg[i] == 0x7fffffff;
                 arow[i] = none ? 0.f : fmaxf(0.f, best[i] / e2);
                 tau_row[k][i] = none ? 0 : bestg[i] * stride;
+                amp_row[i] = arow[i];
             }
             // this lane's A row r: its pick sits in lanes 16 (r / 4) .. + 15, element r % 4
             const int src = (r >> 2) * 16;
@@ -342,7 +395,7 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
             }
             amp_mine[k] = a_sel;
             tau_mine[k] = t_sel;
-            if (k + 1 < K) {                            // w_l -= a hhat_l exp(i w_l tau)
+            if (!RHO && k + 1 < K) {                    // w_l -= a hhat_l exp(i w_l tau)
                 float2 u = phasor_int(mod_small(l_first * t_sel, T, invT), twoinvT);
                 const float2 step = phasor_int(mod_small(2 * t_sel, T, invT), twoinvT);
 #pragma unroll
@@ -1017,10 +1070,18 @@ static InitGrid init_grid(const srt3d_params& p) {
     return g;
 }
 
-// workspace: per-workgroup photon-count maxima, then the grid table (B-operand fragments)
+// Greedy picks after the first update the correlation kept in registers (see init_rho_kernel)
+// when there are several and it fits: at most 16 column tiles.
+static bool init_keeps_correlation(const srt3d_params& p, const InitGrid& g) {
+    return p.K_max >= 2 && g.NT <= 16 && g.KS <= 16;
+}
+
+// workspace: per-workgroup photon-count maxima, the grid table (B-operand fragments), then the
+// atom's autocorrelation on 16 NT grid lags
 size_t init_ws_bytes(const srt3d_params& p) {
     const InitGrid g = init_grid(p);
-    return (size_t)kInitBlocksMax * sizeof(int) + (size_t)g.NT * g.KS * 64 * sizeof(float);
+    return (size_t)kInitBlocksMax * sizeof(int) + (size_t)g.NT * g.KS * 64 * sizeof(float) +
+           (size_t)16 * g.NT * sizeof(float);
 }
 
 #define SRT3D_BY_K(K_, CALL)                            \
@@ -1057,23 +1118,34 @@ hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int 
     int* part = reinterpret_cast<int*>(ws);
     float* EB = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + (size_t)kInitBlocksMax * sizeof(int));
     const int tab = g.NT * g.KS * 64;
+    float* rho = EB + tab;
     hipLaunchKernelGGL(init_grid_table_kernel, dim3((tab + 255) / 256), dim3(256), 0, s, p.T, p.m, g.stride, g.G, g.KS,
                        g.NT, EB);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    const bool keep = init_keeps_correlation(p, g);
+    if (keep) {
+        hipLaunchKernelGGL(init_rho_kernel, dim3((16 * g.NT + 255) / 256), dim3(256), 0, s, st.hhat, p.T, p.m, g.stride,
+                           g.G, 16 * g.NT, rho);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     int dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
     int64_t blocks = ((int64_t)(P + 15) / 16 + 3) / 4;
     const int64_t cap = std::min<int64_t>((int64_t)cus * 8, kInitBlocksMax);
     if (blocks > cap) blocks = cap;
-#define SRT3D_INIT(KSM)                                                                                           \
-    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((init_kernel<KK, KSM>), dim3((unsigned)blocks), dim3(256), 0, s, z, n, \
-                                           st.hhat, st.scal, EB, P, p.T, p.m, g.stride, g.G, g.KS, g.NT, p.r_min, \
-                                           st.t[0], st.alpha[0], st.active[0], part))
-    if (g.KS <= 4) { SRT3D_INIT(4); }
-    else if (g.KS <= 8) { SRT3D_INIT(8); }
-    else if (g.KS <= 16) { SRT3D_INIT(16); }
-    else { SRT3D_INIT(32); }
+#define SRT3D_INIT(KSM, RH)                                                                                      \
+    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((init_kernel<KK, KSM, RH>), dim3((unsigned)blocks), dim3(256), 0, s, z, n, \
+                                           st.hhat, st.scal, EB, rho, P, p.T, p.m, g.stride, g.G, g.KS, g.NT,      \
+                                           p.r_min, st.t[0], st.alpha[0], st.active[0], part))
+    const int ksn = g.KS > g.NT ? g.KS : g.NT;     // with the correlation kept, tiles index registers too
+    if (keep && ksn <= 4) { SRT3D_INIT(4, true); }
+    else if (keep && ksn <= 8) { SRT3D_INIT(8, true); }
+    else if (keep) { SRT3D_INIT(16, true); }
+    else if (g.KS <= 4) { SRT3D_INIT(4, false); }
+    else if (g.KS <= 8) { SRT3D_INIT(8, false); }
+    else if (g.KS <= 16) { SRT3D_INIT(16, false); }
+    else { SRT3D_INIT(32, false); }
 #undef SRT3D_INIT
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(step_sizes_kernel, dim3(1), dim3(256), 0, s, part, (int)blocks, p.K_max, p.eta_t, p.eta_a,
