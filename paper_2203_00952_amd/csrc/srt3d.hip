@@ -25,7 +25,7 @@ namespace srt3d {
 
 constexpr float kCholEps = 1e-5f;    // pivot <= kCholEps * trace counts as singular
 constexpr int kTile = 16;            // denoiser tile edge (pixels)
-constexpr int kInitBlocksMax = 4096; // init workgroups (bounds the partial-max buffer)
+constexpr int kInitBlocksMax = 4096; // init workgroups at most; also the number of photon-count partials
 
 struct IterArgs {
     int rows, cols, P, T, m, K, R, Rb;
@@ -127,10 +127,9 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 
 // ----------------------------------------------------------------------------- frame constants
 // scal: [0] n_max, [1] gamma_t, [2] gamma_alpha, [3] tau_z, [4] sum |hhat|^2, [5] sum w^2 |hhat|^2
-__global__ __launch_bounds__(256) void frame_constants_kernel(const double* __restrict__ irf, int irf_len,
-                                                              int origin, int T, int m, float tau_z_param,
-                                                              float* __restrict__ hhat_out,
-                                                              float* __restrict__ scal) {
+// One workgroup; the harmonics are spread over its waves (one or two each at 16 waves).
+__device__ void frame_constants_block(const double* __restrict__ irf, int irf_len, int origin, int T, int m,
+                                      float tau_z_param, float* __restrict__ hhat_out, float* __restrict__ scal) {
     __shared__ double s_e2[SRT3D_MAX_M_RECON], s_et[SRT3D_MAX_M_RECON];
     __shared__ double s_mom[3];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -200,12 +199,13 @@ __global__ __launch_bounds__(256) void frame_constants_kernel(const double* __re
 // (l tau_g) mod T.  One wave takes 16 pixels: its Y rows stay in registers as the A operand of
 // v_mfma_f32_16x16x4_f32, E is read as prebuilt B-operand fragments, and the argmax of every row
 // is folded into the epilogue of each 16-column tile (larger c, then smaller tau).  Each greedy
-// pick subtracts its atom from the working sketch w and the product is redone.
+// pick removes its atom: either from the working sketch w, after which the product is redone, or
+// (RHO) from the kept correlation directly, by the atom's autocorrelation.
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // EB[(nt * KS + ks) * 64 + lane] = E[4 ks + lane / 16][16 nt + lane % 16], zero outside 2m x G.
-__global__ void init_grid_table_kernel(int T, int m, int stride, int G, int KS, int NT, float* __restrict__ EB) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void grid_table_entry(int idx, int T, int m, int stride, int G, int KS, int NT,
+                                                 float* __restrict__ EB) {
     if (idx >= NT * KS * 64) return;
     const int lane = idx & 63, ks = (idx >> 6) % KS, nt = (idx >> 6) / KS;
     const int k = 4 * ks + (lane >> 4), g = 16 * nt + (lane & 15);
@@ -223,11 +223,10 @@ __global__ void init_grid_table_kernel(int T, int m, int stride, int G, int KS, 
 // rho[d] = Re sum_l conj(hhat_l) hhat_l e^{-i w_l d stride} = sum_l |hhat_l|^2 cos(w_l d stride), even
 // in d.  Removing the atom a hhat_l e^{i w_l tau_k} from the working sketch lowers the grid
 // correlation at tau by exactly a rho(tau - tau_k), so the greedy picks after the first update
-// the correlation instead of recomputing it.  Exact integer phase, FP64 sum, stored as FP32.
-__global__ void init_rho_kernel(const float* __restrict__ hhat, int T, int m, int stride, int G, int GP,
-                                float* __restrict__ rho) {
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= GP) return;
+// the correlation instead of recomputing it.  Exact integer phase, FP64 sum of the FP32 hhat
+// the correlation itself uses, stored as FP32; lags past the grid are 0 (read only with a zero
+// amplitude).
+__device__ __forceinline__ float rho_entry(const float* __restrict__ hhat, int d, int T, int m, int stride, int G) {
     double acc = 0.0;
     if (d < G) {
         const int64_t lag = ((int64_t)d * stride) % T;
@@ -237,7 +236,53 @@ __global__ void init_rho_kernel(const float* __restrict__ hhat, int T, int m, in
             acc += (hr * hr + hi * hi) * cospi(2.0 * (double)ph / (double)T);
         }
     }
-    rho[d] = (float)acc;          // lags past the grid: 0 (read only with a zero amplitude)
+    return (float)acc;
+}
+
+// Everything a frame needs before init, in one launch: workgroup 0 computes the frame constants
+// and (GP > 0) tabulates rho on GP lags; the next `tb` workgroups build the grid table for init's
+// matrix product; the rest each write the largest photon count of one stretch of 1024 cpt pixels.
+constexpr int kSetupThreads = 1024;
+__global__ __launch_bounds__(kSetupThreads) void frame_setup_kernel(
+    const double* __restrict__ irf, int irf_len, int origin, int T, int m, float tau_z_param, int stride, int G,
+    int KS, int NT, int GP, int tb, const int32_t* __restrict__ n, int P, int cpt, float* __restrict__ hhat,
+    float* __restrict__ scal, float* __restrict__ EB, float* __restrict__ rho, int* __restrict__ nmax_part) {
+    if (blockIdx.x > tb) {
+        __shared__ int s_w[kSetupThreads / 64];
+        const int b = blockIdx.x - tb - 1;
+        const int64_t base = (int64_t)b * kSetupThreads * cpt + threadIdx.x;
+        int v = 0;
+        for (int i = 0; i < cpt; ++i) {
+            const int64_t q = base + (int64_t)i * kSetupThreads;
+            if (q < P) v = max(v, n[q]);
+        }
+        for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+        if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int i = 1; i < kSetupThreads / 64; ++i) v = max(v, s_w[i]);
+            nmax_part[b] = v;
+        }
+        return;
+    }
+    if (blockIdx.x > 0) {
+        grid_table_entry((blockIdx.x - 1) * kSetupThreads + threadIdx.x, T, m, stride, G, KS, NT, EB);
+        return;
+    }
+    frame_constants_block(irf, irf_len, origin, T, m, tau_z_param, hhat, scal);
+    if (GP > 0) {
+        __syncthreads();                    // hhat written by this workgroup
+        for (int d = threadIdx.x; d < GP; d += kSetupThreads) rho[d] = rho_entry(hhat, d, T, m, stride, G);
+    }
+}
+
+// n_max and the step sizes of eq. (8).
+__device__ __forceinline__ void step_sizes_store(int nmax_i, int K, float eta_t, float eta_a, float* __restrict__ scal) {
+    const double nmax = (double)nmax_i;
+    const double e2 = (double)scal[4], et = (double)scal[5];
+    scal[0] = (float)nmax;
+    scal[1] = nmax > 0 ? (float)((double)eta_t / (2.0 * nmax * et)) : 0.f;
+    scal[2] = nmax > 0 ? (float)((double)eta_a / (2.0 * nmax * K * e2)) : 0.f;
 }
 
 // RHO: the first pick's correlation stays in LDS (NT <= KSMAX column tiles, 16 bytes per lane and
@@ -245,12 +290,13 @@ __global__ void init_rho_kernel(const float* __restrict__ hhat, int T, int m, in
 // updated working sketch.
 template <int K, int KSMAX, bool RHO>
 __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, const int32_t* __restrict__ n,
-                                                   const float* __restrict__ hhat, const float* __restrict__ scal,
+                                                   const float* __restrict__ hhat, float* __restrict__ scal,
                                                    const float* __restrict__ EB, const float* __restrict__ rho, int P,
                                                    int T, int m, int stride, int G, int KS, int NT, float r_min,
                                                    float* __restrict__ t_out, float* __restrict__ a_out,
-                                                   uint8_t* __restrict__ act_out, int* __restrict__ nmax_part) {
-    __shared__ int s_nmax[4];
+                                                   uint8_t* __restrict__ act_out,
+                                                   const int* __restrict__ nmax_part, int nparts, float eta_t,
+                                                   float eta_a) {
     __shared__ float s_rho[RHO ? 16 * KSMAX : 1];
     __shared__ v4f s_C[RHO ? 4 * KSMAX * 64 : 1];     // [wave][column tile][lane]
     if constexpr (RHO) {
@@ -269,7 +315,6 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
         const int k = 4 * ks + kq;
         hl[ks] = (ks < KS && k < 2 * m) ? reinterpret_cast<const float2*>(hhat)[k / 2] : make_float2(0.f, 0.f);
     }
-    int nmax = 0;
     for (int grp = blockIdx.x * (blockDim.x >> 6) + wv; grp < groups; grp += waves_total) {
         const int prow = grp * 16 + r;
         const bool rv = prow < P;
@@ -281,7 +326,6 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
                                                   : make_float2(0.f, 0.f);
         }
         const int np = rv ? n[prow] : 0;
-        nmax = max(nmax, np);
         int tau_row[K][4];                              // picks of C rows 4 kq + i
         int tau_mine[K];                                // picks of A row r
         float amp_mine[K];
@@ -424,35 +468,14 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
             }
         }
     }
-    for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
-    if (lane == 0) s_nmax[wv] = nmax;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int v = s_nmax[0];
-        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) v = max(v, s_nmax[i]);
-        nmax_part[blockIdx.x] = v;
+    if (blockIdx.x == 0 && wv == 0) {                  // n_max and the step sizes (eq. 8)
+        int v = 0;
+        for (int i = lane; i < nparts; i += 64) v = max(v, nmax_part[i]);
+        for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+        if (lane == 0) step_sizes_store(v, K, eta_t, eta_a, scal);
     }
 }
 
-__global__ __launch_bounds__(256) void step_sizes_kernel(const int* __restrict__ nmax_part, int parts, int K,
-                                                         float eta_t, float eta_a, float* __restrict__ scal) {
-    __shared__ int s[256];
-    int v = 0;
-    for (int i = threadIdx.x; i < parts; i += blockDim.x) v = max(v, nmax_part[i]);
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + o]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double nmax = (double)s[0];
-        const double e2 = (double)scal[4], et = (double)scal[5];
-        scal[0] = (float)nmax;
-        scal[1] = nmax > 0 ? (float)((double)eta_t / (2.0 * nmax * et)) : 0.f;
-        scal[2] = nmax > 0 ? (float)((double)eta_a / (2.0 * nmax * K * e2)) : 0.f;
-    }
-}
 
 // ----------------------------------------------------------------------------- data step
 // Four lanes per pixel: lane `sub` takes harmonics l in (lo, hi], a contiguous quarter of 1..m,
@@ -1073,18 +1096,18 @@ static InitGrid init_grid(const srt3d_params& p) {
     return g;
 }
 
-// Greedy picks after the first update the correlation kept in registers (see init_rho_kernel)
+// Greedy picks after the first update the correlation kept in LDS (see rho_entry)
 // when there are several and it fits: at most 16 column tiles.
 static bool init_keeps_correlation(const srt3d_params& p, const InitGrid& g) {
     return p.K_max >= 2 && g.NT <= 16 && g.KS <= 16;
 }
 
-// workspace: per-workgroup photon-count maxima, the grid table (B-operand fragments), then the
-// atom's autocorrelation on 16 NT grid lags
+// workspace: photon-count maxima of stretches of pixels (kInitWsHead bytes), the grid table
+// (B-operand fragments), then the atom's autocorrelation on 16 NT grid lags
+constexpr size_t kInitWsHead = (size_t)kInitBlocksMax * sizeof(int) + 256;
 size_t init_ws_bytes(const srt3d_params& p) {
     const InitGrid g = init_grid(p);
-    return (size_t)kInitBlocksMax * sizeof(int) + (size_t)g.NT * g.KS * 64 * sizeof(float) +
-           (size_t)16 * g.NT * sizeof(float);
+    return kInitWsHead + (size_t)g.NT * g.KS * 64 * sizeof(float) + (size_t)16 * g.NT * sizeof(float);
 }
 
 #define SRT3D_BY_K(K_, CALL)                            \
@@ -1113,24 +1136,22 @@ size_t init_ws_bytes(const srt3d_params& p) {
 hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int irf_len, int irf_origin,
                        const srt3d_params& p, const srt3d_state& st, void* ws, hipStream_t s) {
     const int P = p.rows * p.cols;
-    hipLaunchKernelGGL(frame_constants_kernel, dim3(1), dim3(256), 0, s, irf, irf_len, irf_origin, p.T, p.m,
-                       p.tau_z, st.hhat, st.scal);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     const InitGrid g = init_grid(p);
     int* part = reinterpret_cast<int*>(ws);
-    float* EB = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + (size_t)kInitBlocksMax * sizeof(int));
+    float* EB = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + kInitWsHead);
     const int tab = g.NT * g.KS * 64;
     float* rho = EB + tab;
-    hipLaunchKernelGGL(init_grid_table_kernel, dim3((tab + 255) / 256), dim3(256), 0, s, p.T, p.m, g.stride, g.G, g.KS,
-                       g.NT, EB);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     const bool keep = init_keeps_correlation(p, g);
-    if (keep) {
-        hipLaunchKernelGGL(init_rho_kernel, dim3((16 * g.NT + 255) / 256), dim3(256), 0, s, st.hhat, p.T, p.m, g.stride,
-                           g.G, 16 * g.NT, rho);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    const int tb = (tab + kSetupThreads - 1) / kSetupThreads;
+    // counts per thread: at least 16, and few enough stretches for the kInitBlocksMax partials
+    const int64_t per_part = (int64_t)kSetupThreads * kInitBlocksMax;
+    const int cpt = (int)std::max<int64_t>(16, ((int64_t)P + per_part - 1) / per_part);
+    const int nparts = (int)(((int64_t)P + (int64_t)kSetupThreads * cpt - 1) / ((int64_t)kSetupThreads * cpt));
+    hipLaunchKernelGGL(frame_setup_kernel, dim3(1 + tb + nparts), dim3(kSetupThreads), 0, s, irf, irf_len, irf_origin,
+                       p.T, p.m, p.tau_z, g.stride, g.G, g.KS, g.NT, keep ? 16 * g.NT : 0, tb, n, P, cpt, st.hhat, st.scal,
+                       EB, rho, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     int dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
@@ -1140,7 +1161,8 @@ hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int 
 #define SRT3D_INIT(KSM, RH)                                                                                      \
     SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((init_kernel<KK, KSM, RH>), dim3((unsigned)blocks), dim3(256), 0, s, z, n, \
                                            st.hhat, st.scal, EB, rho, P, p.T, p.m, g.stride, g.G, g.KS, g.NT,      \
-                                           p.r_min, st.t[0], st.alpha[0], st.active[0], part))
+                                           p.r_min, st.t[0], st.alpha[0], st.active[0], part, nparts, p.eta_t,     \
+                                           p.eta_a))
     const int ksn = g.KS > g.NT ? g.KS : g.NT;     // with the correlation kept, tiles index registers too
     if (keep && ksn <= 4) { SRT3D_INIT(4, true); }
     else if (keep && ksn <= 8) { SRT3D_INIT(8, true); }
@@ -1150,9 +1172,6 @@ hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int 
     else if (g.KS <= 16) { SRT3D_INIT(16, false); }
     else { SRT3D_INIT(32, false); }
 #undef SRT3D_INIT
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(step_sizes_kernel, dim3(1), dim3(256), 0, s, part, (int)blocks, p.K_max, p.eta_t, p.eta_a,
-                       st.scal);
     return hipGetLastError();
 }
 

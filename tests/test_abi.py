@@ -56,10 +56,10 @@ def test_workspace_queries(lib):
     assert lib.srt3d_hist_workspace_bytes(16384, 4, 0) == 0
     p = L._Params()
     lib.srt3d_params_default(ctypes.byref(p), 32, 32, 1024, 4, 1)
-    # per-workgroup maxima of n, the grid table: T=1024, m=4 -> stride 32, 32 grid points
-    # (2 column tiles) x 2 k-steps x 64 lanes of FP32 B-operand fragments, then the atom's
-    # autocorrelation on 16 lags per column tile (FP32)
-    assert lib.srt3d_init_workspace_bytes(ctypes.byref(p)) == 4096 * 4 + 2 * 2 * 64 * 4 + 2 * 16 * 4
+    # per-workgroup maxima of n and a completion counter (256 bytes), the grid table: T=1024, m=4
+    # -> stride 32, 32 grid points (2 column tiles) x 2 k-steps x 64 lanes of FP32 B-operand
+    # fragments, then the atom's autocorrelation on 16 lags per column tile (FP32)
+    assert lib.srt3d_init_workspace_bytes(ctypes.byref(p)) == 4096 * 4 + 256 + 2 * 2 * 64 * 4 + 2 * 16 * 4
     p.K_max = 4
     assert lib.srt3d_init_workspace_bytes(ctypes.byref(p)) == 0
 
