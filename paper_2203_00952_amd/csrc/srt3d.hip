@@ -478,6 +478,16 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
 
 
 // ----------------------------------------------------------------------------- data step
+// Moves between the four lanes of a pixel (an aligned quad, always active together): DPP quad
+// permutes, one VALU instruction each instead of an LDS round trip, the same values.
+template <int CTRL>
+__device__ __forceinline__ float quad_dpp(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float quad_xor1(float v) { return quad_dpp<0xB1>(v); }    // lanes 1, 0, 3, 2
+__device__ __forceinline__ float quad_xor2(float v) { return quad_dpp<0x4E>(v); }    // lanes 2, 3, 0, 1
+__device__ __forceinline__ float quad_first(float v) { return quad_dpp<0x00>(v); }   // lane 0 of the quad
+
 // Four lanes per pixel: lane `sub` takes harmonics l in (lo, hi], a contiguous quarter of 1..m,
 // reads its slice of the pixel's sketch directly (the four lanes cover the row contiguously)
 // and keeps a phasor recurrence re-anchored at the start of its slice and every 8 harmonics.
@@ -507,13 +517,12 @@ __device__ __forceinline__ void residual_pass(const Src& src, int lo, int hi, in
                                               bool depth) {
     // each lane anchors at the first harmonic of its slice; lane 0 of the pixel's group holds
     // harmonic 1, whose phasor drives everyone's recurrence
-    const int base = (threadIdx.x & 63) & ~(kLanesPerPixel - 1);
     float2 u[K], u1[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         u[k] = on[k] ? phasor(lo + 1, tk[k], T, invT, twoinvT) : make_float2(1.f, 0.f);
-        u1[k].x = __shfl(u[k].x, base, 64);
-        u1[k].y = __shfl(u[k].y, base, 64);
+        u1[k].x = quad_first(u[k].x);
+        u1[k].y = quad_first(u[k].y);
     }
     const float w1 = 6.283185307179586f * invT;
     // harmonic l = l0 + 1, l0 = lo + j; MS bounds the slice at compile time so that a register
@@ -548,8 +557,8 @@ __device__ __forceinline__ void residual_pass(const Src& src, int lo, int hi, in
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        gsum[k] += __shfl_xor(gsum[k], 1, 64);
-        gsum[k] += __shfl_xor(gsum[k], 2, 64);
+        gsum[k] += quad_xor1(gsum[k]);
+        gsum[k] += quad_xor2(gsum[k]);
     }
 }
 
@@ -966,10 +975,10 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
             tk[k] = s_td[c];
             float nm, dn;
             id_part<K, R>(s_td, s_a1, s_r1, E1, ti + R, tj + R, k, Tf, invT, tau_z, sub, nm, dn);
-            nm += __shfl_xor(nm, 1, 64);
-            dn += __shfl_xor(dn, 1, 64);
-            nm += __shfl_xor(nm, 2, 64);
-            dn += __shfl_xor(dn, 2, 64);
+            nm += quad_xor1(nm);
+            dn += quad_xor1(dn);
+            nm += quad_xor2(nm);
+            dn += quad_xor2(dn);
             rt[k] = was[k] ? id_ratio(nm, dn) : 0.f;
         }
         const float nq = (float)n[pix];
