@@ -225,15 +225,21 @@ __device__ __forceinline__ void grid_table_entry(int idx, int T, int m, int stri
 // correlation at tau by exactly a rho(tau - tau_k), so the greedy picks after the first update
 // the correlation instead of recomputing it.  Exact integer phase, FP64 sum of the FP32 hhat
 // the correlation itself uses, stored as FP32; lags past the grid are 0 (read only with a zero
-// amplitude).
+// amplitude).  cos(w_l lag) follows from the first harmonic's phasor by an FP64 complex
+// recurrence (m - 1 products: rounding near 1e-15, far below the FP32 result).
 __device__ __forceinline__ float rho_entry(const float* __restrict__ hhat, int d, int T, int m, int stride, int G) {
     double acc = 0.0;
     if (d < G) {
         const int64_t lag = ((int64_t)d * stride) % T;
+        double s1, c1;
+        sincospi(2.0 * (double)lag / (double)T, &s1, &c1);
+        double c = c1, s = s1;
         for (int l = 1; l <= m; ++l) {
             const double hr = hhat[2 * (l - 1)], hi = hhat[2 * (l - 1) + 1];
-            const int64_t ph = ((int64_t)l * lag) % T;
-            acc += (hr * hr + hi * hi) * cospi(2.0 * (double)ph / (double)T);
+            acc += (hr * hr + hi * hi) * c;
+            const double cn = c * c1 - s * s1;
+            s = c * s1 + s * c1;
+            c = cn;
         }
     }
     return (float)acc;
