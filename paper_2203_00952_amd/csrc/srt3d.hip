@@ -696,25 +696,34 @@ __device__ constexpr float full_moment(int r, int c) {
 }
 
 // Depth denoiser for point k of the pixel at LDS cell (ci, cj); t and act are (E x E cells) x K
-// arrays whose window cells lie within the array.  Returns the new depth.  With one point per
-// pixel and R <= 2 the normal matrix is the full-window sum minus the (few) neighbours that fail
-// the gate -- exact, since all entries are integers below 2^24.  With several points per pixel
-// the K candidates of a window cell share the cell's offsets, so each cell contributes
-// (gated count) x (its weighted monomials) to the matrix and q x (sum of its gated offsets) x
-// (monomials) to the right-hand side: one set of updates per cell instead of per candidate.
-// Entries whose factor is zero for a given offset are skipped at compile time.
+// arrays whose window cells lie within the array.  With one point per pixel and R <= 2 the
+// normal matrix is the full-window sum minus the (few) neighbours that fail the gate -- exact,
+// since all entries are integers below 2^24.  With several points per pixel the K candidates of
+// a window cell share the cell's offsets, so each cell contributes (gated count) x (its weighted
+// monomials) to the matrix and q x (sum of its gated offsets) x (monomials) to the right-hand
+// side: one set of updates per cell instead of per candidate.  Entries whose factor is zero for
+// a given offset are skipped at compile time.
+//
+// The window is summed in two parts, rows -R..0 and rows 1..R (each in window order), added as
+// part 0 + part 1: the fused iteration gives the parts to different waves, the stand-alone
+// kernel sums both in one thread, and both get the same bits.
 template <int K, int R>
-__device__ __forceinline__ float dd_point(const float* st, const uint8_t* sa, int E, int ci, int cj, int k, float Tf,
-                                          float invT, float tau_z, float lambda_z) {
+__device__ __forceinline__ void dd_start(float (&M)[4][4], float (&b)[4], bool first) {
     constexpr bool SUB = (K == 1) && (R <= 2);
-    const float tq = st[(ci * E + cj) * K + k];
-    float M[4][4], b[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 4; ++r) {
+        b[r] = 0.f;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) M[r][c] = SUB ? full_moment<R>(r, c) : 0.f;
+        for (int c = 0; c < 4; ++c) M[r][c] = (SUB && first) ? full_moment<R>(r, c) : 0.f;
+    }
+}
+
+template <int K, int R, int DI0, int DI1>
+__device__ __forceinline__ void dd_rows(const float* st, const uint8_t* sa, int E, int ci, int cj, float tq, float Tf,
+                                        float invT, float tau_z, float (&M)[4][4], float (&b)[4]) {
+    constexpr bool SUB = (K == 1) && (R <= 2);
 #pragma unroll
-    for (int di = -R; di <= R; ++di) {
+    for (int di = DI0; di <= DI1; ++di) {
 #pragma unroll
         for (int dj = -R; dj <= R; ++dj) {
             const float q = win_q<R>(di, dj);
@@ -744,6 +753,31 @@ __device__ __forceinline__ float dd_point(const float* st, const uint8_t* sa, in
             if (dj != 0 && r2 != 0) M[2][3] += sq * (dj * r2);
         }
     }
+}
+
+// The ten distinct matrix entries and the right-hand side of a part, for passing it on.
+constexpr int kDDPart = 14;
+__device__ __forceinline__ void dd_pack(const float (&M)[4][4], const float (&b)[4], float* o) {
+    int i = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = r; c < 4; ++c) o[i++] = M[r][c];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[i++] = b[r];
+}
+__device__ __forceinline__ void dd_add_part(float (&M)[4][4], float (&b)[4], const float* o) {
+    int i = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = r; c < 4; ++c) M[r][c] += o[i++];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) b[r] += o[i++];
+}
+
+// Solve the combined equations (upper triangle of M) and return the new depth.
+__device__ __forceinline__ float dd_solve(float (&M)[4][4], float (&b)[4], float tq, float Tf, float lambda_z) {
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -753,6 +787,20 @@ __device__ __forceinline__ float dd_point(const float* st, const uint8_t* sa, in
         if (!ldl_x0<3>(M, b, a)) a = b[0] * __builtin_amdgcn_rcpf(M[0][0] > 0.f ? M[0][0] : 1.f);
     }
     return wrap_t(tq + lambda_z * a, Tf);
+}
+
+template <int K, int R>
+__device__ __forceinline__ float dd_point(const float* st, const uint8_t* sa, int E, int ci, int cj, int k, float Tf,
+                                          float invT, float tau_z, float lambda_z) {
+    const float tq = st[(ci * E + cj) * K + k];
+    float M[4][4], b[4], M1[4][4], b1[4], o[kDDPart];
+    dd_start<K, R>(M, b, true);
+    dd_rows<K, R, -R, 0>(st, sa, E, ci, cj, tq, Tf, invT, tau_z, M, b);
+    dd_start<K, R>(M1, b1, false);
+    dd_rows<K, R, 1, R>(st, sa, E, ci, cj, tq, Tf, invT, tau_z, M1, b1);
+    dd_pack(M1, b1, o);
+    dd_add_part(M, b, o);
+    return dd_solve(M, b, tq, Tf, lambda_z);
 }
 
 // Intensity denoiser: gated weighted mean of r = n * alpha around point k of cell (ci, cj).
@@ -931,6 +979,7 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
     __shared__ float s_r1[E1Y * E1 * K];         // n * alpha after the data step
     __shared__ uint8_t s_a1[E1Y * E1 * K];
     __shared__ float2 s_h[SRT3D_MAX_M_RECON];
+    __shared__ float s_ddp[(K == 1 && !DD_DONE && E1Y * E1 <= kIterThreads / 2) ? E1Y * E1 * kDDPart : 1];
     const int i0 = blockIdx.y * kIterTY, j0 = blockIdx.x * kIterTX;
     // The data step's sketch slice (this thread's pixel and harmonics) is loaded first, into
     // registers, and stays in flight through the denoisers: the barriers below order LDS only.
@@ -956,7 +1005,41 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
     load_region<K, true>(s_td, s_a1, s_r1, E1Y, E1, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
     lds_barrier();
     const float Tf = (float)A.T, invT = 1.0f / Tf, tau_z = scal[3];
-    if constexpr (!DD_DONE) {
+    constexpr bool SPLIT_DD = !DD_DONE && K == 1 && E1Y * E1 <= kIterThreads / 2;
+    if constexpr (SPLIT_DD) {
+        // depth denoiser on the tile + R ring, one cell per thread of each half of the block:
+        // waves 0-3 sum window rows -R..0, waves 4-7 rows 1..R and pass theirs on through LDS
+        const bool second = threadIdx.x >= kIterThreads / 2;            // uniform per wave
+        const int idx = threadIdx.x - (second ? kIterThreads / 2 : 0);
+        float M[4][4], b[4];
+        bool fit = false;
+        float tq = 0.f;
+        if (idx < E1Y * E1) {
+            const int ci = idx / E1 + R, cj = idx % E1 + R;                // cell in the E2 region
+            const int c2 = ci * E2 + cj;
+            tq = s_t2[c2];
+            fit = s_a2[c2] != 0;
+            if (fit) {
+                dd_start<K, R>(M, b, !second);
+                if (second) {
+                    dd_rows<K, R, 1, R>(s_t2, s_a2, E2, ci, cj, tq, Tf, invT, tau_z, M, b);
+                    dd_pack(M, b, s_ddp + idx * kDDPart);
+                } else {
+                    dd_rows<K, R, -R, 0>(s_t2, s_a2, E2, ci, cj, tq, Tf, invT, tau_z, M, b);
+                }
+            }
+        }
+        lds_barrier();
+        if (!second && idx < E1Y * E1) {
+            if (fit) {
+                dd_add_part(M, b, s_ddp + idx * kDDPart);
+                s_td[idx] = dd_solve(M, b, tq, Tf, A.lambda_z);
+            } else {
+                s_td[idx] = tq;
+            }
+        }
+        lds_barrier();
+    } else if constexpr (!DD_DONE) {
         // depth denoiser on the tile + R ring
         for (int idx = threadIdx.x; idx < E1Y * E1 * K; idx += blockDim.x) {
             const int k = idx % K, cell = idx / K;
