@@ -83,6 +83,38 @@ def sketch(stamps, offsets, T: int, m: int, pixels=None):
     return normalise(S, n), n
 
 
+def sketch_event_sums(pix, stamps, P: int, T: int, m: int):
+    """Unnormalised sums of an arrival-order event stream (Section 2: the sketch is updated
+    online, photon by photon, as each one arrives).
+
+    Event e = (pix[e], stamps[e]) adds exp(i w_l x_e) to pixel pix[e], in stream order.  An event
+    whose pixel index lies outside [0, P) belongs to no pixel: it is dropped and counted.  Stamps
+    are folded as in sketch_sums.  Returns (S complex128 [P, m], n int64 [P], dropped, folded)
+    with `folded` the number of kept events whose stamp lay outside [0, T).
+    """
+    pix = np.asarray(pix, dtype=np.int64)
+    raw = np.asarray(stamps, dtype=np.int64)
+    keep = (pix >= 0) & (pix < P)
+    dropped = int(np.count_nonzero(~keep))
+    pix, raw = pix[keep], raw[keep]
+    folded = int(np.count_nonzero((raw < 0) | (raw >= T)))
+    x = np.mod(raw, T)
+    S = np.zeros((P, m), dtype=np.complex128)
+    for ell in range(1, m + 1):
+        ang = 2.0 * np.pi * np.mod(ell * x, T) / T
+        col = np.zeros(P, dtype=np.complex128)
+        np.add.at(col, pix, np.cos(ang) + 1j * np.sin(ang))     # one update per event, in order
+        S[:, ell - 1] = col
+    n = np.bincount(pix, minlength=P).astype(np.int64)
+    return S, n, dropped, folded
+
+
+def sketch_events(pix, stamps, P: int, T: int, m: int):
+    """Per-pixel sketch z [P, m] and photon count n [P] of an event stream (see sketch_event_sums)."""
+    S, n, _, _ = sketch_event_sums(pix, stamps, P, T, m)
+    return normalise(S, n), n
+
+
 def dft_columns(T: int, m: int) -> np.ndarray:
     """F[t, l-1] = exp(i w_l t) for t = 0..T-1 with exact phase reduction."""
     t = np.arange(T, dtype=np.int64)

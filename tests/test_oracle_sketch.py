@@ -140,3 +140,66 @@ def test_pixel_subset():
     zs, ns = OS.sketch(*_csr(pixels), T, m, pixels=sel)
     np.testing.assert_array_equal(ns, n[sel])
     np.testing.assert_allclose(zs, z[sel], atol=0)
+
+
+# ----------------------------------------------------------------------------- event streams
+def _stream(rng, P, T, counts):
+    """A shuffled arrival-order stream holding `counts[p]` uniform stamps for pixel p."""
+    pix = np.repeat(np.arange(P), counts)
+    st = rng.integers(0, T, pix.size)
+    order = rng.permutation(pix.size)
+    return pix[order], st[order]
+
+
+def test_event_stream_matches_per_pixel_loop():
+    """Each pixel's sum is the correctly rounded per-photon loop over its events."""
+    rng = np.random.default_rng(11)
+    P, T, m = 12, 997, 7
+    pix, st = _stream(rng, P, T, rng.integers(0, 40, P))
+    z, n = OS.sketch_events(pix, st, P, T, m)
+    for p in range(P):
+        zl, nl = OS.sketch_loop(st[pix == p], T, m)
+        assert nl == n[p]
+        np.testing.assert_allclose(zl, z[p], atol=1e-14)
+
+
+def test_event_stream_order_does_not_matter():
+    rng = np.random.default_rng(12)
+    P, T, m = 40, 4096, 16
+    pix, st = _stream(rng, P, T, rng.integers(0, 300, P))
+    z, n = OS.sketch_events(pix, st, P, T, m)
+    for _ in range(3):
+        o = rng.permutation(pix.size)
+        z2, n2 = OS.sketch_events(pix[o], st[o], P, T, m)
+        np.testing.assert_array_equal(n2, n)
+        np.testing.assert_allclose(z2, z, atol=1e-12)
+
+
+def test_event_stream_chunks_add_up():
+    """The sums are linear in the stream: any split into consecutive chunks adds up to the whole."""
+    rng = np.random.default_rng(13)
+    P, T, m = 25, 2048, 8
+    pix, st = _stream(rng, P, T, rng.integers(0, 200, P))
+    S, n, _, _ = OS.sketch_event_sums(pix, st, P, T, m)
+    cut = pix.size // 3
+    S1, n1, _, _ = OS.sketch_event_sums(pix[:cut], st[:cut], P, T, m)
+    S2, n2, _, _ = OS.sketch_event_sums(pix[cut:], st[cut:], P, T, m)
+    np.testing.assert_array_equal(n1 + n2, n)
+    np.testing.assert_allclose(S1 + S2, S, atol=1e-10)
+
+
+def test_event_stream_closed_forms_and_bad_events():
+    T, m, P = 64, 5, 4
+    # pixel 0: one photon (|z| = 1); pixel 1: every stamp once (z = 0, eq. 4 with a uniform
+    # background); pixel 2: nothing; pixel 3: a folded stamp.  Events for pixels -1 and 4 are
+    # outside the frame.
+    pix = [0, 4] + [1] * T + [-1, 3, 3]
+    st = [9, 1] + list(range(T)) + [5, 70, 6]
+    S, n, dropped, folded = OS.sketch_event_sums(pix, st, P, T, m)
+    z, _ = OS.sketch_events(pix, st, P, T, m)
+    assert list(n) == [1, T, 0, 2] and dropped == 2 and folded == 1
+    np.testing.assert_allclose(np.abs(z[0]), 1.0, atol=1e-15)
+    np.testing.assert_allclose(z[1], 0.0, atol=1e-13)
+    assert np.all(z[2] == 0)
+    z3, _ = OS.sketch(*_csr([[70 % T, 6]]), T, m)
+    np.testing.assert_allclose(z[3], z3[0], atol=1e-15)
