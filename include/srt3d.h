@@ -156,6 +156,28 @@ int srt3d_sketch_binned(const int32_t* d_stamps, int64_t N, const int64_t* d_off
                         double* d_acc, int64_t* d_nacc, int32_t* d_err, void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Sketch of an arrival-order event stream -- Section 2 (the sketch is updated online as each
+ * photon arrives) and eq. (3): event e = (d_pix[e], d_stamps[e]) adds exp(i w_l x_e) to its
+ * pixel.  The stream is grouped by pixel on the device (counting sort into d_ws) and sketched
+ * as by srt3d_sketch_binned (m <= 32) or srt3d_sketch (m > 32); with the binned pass the result
+ * does not depend on the order of the events (integer histograms).  Six kernel launches.
+ *   d_pix     int32 [N] pixel index of each event; events with an index outside [0, P) are
+ *             dropped and counted in d_err[1]
+ *   d_stamps  int32 [N] time stamps; stamps outside [0, T) are folded mod T and counted in
+ *             d_err[0]
+ *   d_ws      workspace of srt3d_sketch_events_workspace_bytes(N, P) bytes, 256-byte aligned
+ *             (per-pixel counts, CSR offsets, the grouped stamps); overwritten by each call
+ *   d_table, d_z, d_n, d_acc, d_nacc, d_err: as srt3d_sketch
+ * Constraints: as srt3d_sketch.  srt3d_sketch_events_workspace_bytes returns 0 for N < 0 or
+ * P < 1; a smaller workspace gives SRT3D_ENOMEM.
+ * ------------------------------------------------------------------------------------- */
+size_t srt3d_sketch_events_workspace_bytes(int64_t N, int32_t P);
+int srt3d_sketch_events(const int32_t* d_pix, const int32_t* d_stamps, int64_t N, int32_t P,
+                        int32_t T, int32_t m, const float* d_table, float* d_z, int32_t* d_n,
+                        double* d_acc, int64_t* d_nacc, int32_t* d_err, void* d_ws,
+                        size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * Sketch of per-pixel ToA histograms -- eq. (2) with unit bins [t, t+1), then eq. (3):
  *     S_l = sum_t H[p][t] exp(i w_l t),  n = sum_t H[p][t],  z = S / n,
  * computed as the product H [P x T] . F [T x 2m] with F the cos/sin DFT columns.

@@ -16,5 +16,6 @@ from ._lib import (  # noqa: F401
     phase_indices,
     phase_table,
     sketch,
+    sketch_events,
     sketch_from_hist,
 )

@@ -46,6 +46,9 @@ _SIGS = {
     "srt3d_phase_table": (_I32, [_I32, _VP, _VP]),
     "srt3d_sketch": (_I32, [_VP, _I64, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "srt3d_sketch_binned": (_I32, [_VP, _I64, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "srt3d_sketch_events_workspace_bytes": (_SZ, [_I64, _I32]),
+    "srt3d_sketch_events": (_I32, [_VP, _VP, _I64, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ,
+                                   _VP]),
     "srt3d_hist_workspace_bytes": (_SZ, [_I32, _I32, _I32]),
     "srt3d_hist_prepare": (_I32, [_I32, _I32, _I32, _VP, _SZ, _VP]),
     "srt3d_sketch_from_hist": (_I32, [_VP, _I32, _I32, _I32, _I32, _VP, _SZ, _VP, _VP, _VP]),
@@ -161,6 +164,37 @@ def sketch(stamps: torch.Tensor, offsets: torch.Tensor, T: int, m: int, *, acc=N
     _check(getattr(_lib(), name)(ps, stamps.numel(), po, P, T, m, _dev(table, torch.float32, "table"),
                                  _dev(z, torch.float32, "z"), _dev(n, torch.int32, "n"), _ptr(acc), _ptr(nacc),
                                  _ptr(err), _stream(dev)), name)
+    return z, n
+
+
+def sketch_events(pix: torch.Tensor, stamps: torch.Tensor, P: int, T: int, m: int, *, acc=None, nacc=None,
+                  err=None, z=None, n=None, table=None, workspace=None):
+    """Sketch of an arrival-order event stream (srt3d_sketch_events): event e adds
+    exp(i w_l stamps[e]) to pixel pix[e].  Returns (z float32 [P, m, 2], n int32 [P])."""
+    dev = stamps.device
+    N = stamps.numel()
+    if pix.numel() != N:
+        raise ValueError("sketch_events: pix and stamps differ in length")
+    pp = _dev(pix, torch.int32, "pix")
+    ps = _dev(stamps, torch.int32, "stamps")
+    z = torch.empty((P, m, 2), dtype=torch.float32, device=dev) if z is None else z
+    n = torch.empty(P, dtype=torch.int32, device=dev) if n is None else n
+    if acc is not None:
+        _dev(acc, torch.float64, "acc")
+        _dev(nacc, torch.int64, "nacc")
+    if err is not None:
+        _dev(err, torch.int32, "err")
+    if table is None:
+        if not (2 <= T and T * 8 <= 65536):
+            raise ValueError("sketch_events: invalid T")
+        table = cached_phase_table(T, dev)
+    nbytes = _lib().srt3d_sketch_events_workspace_bytes(N, P)
+    if nbytes == 0:
+        raise ValueError("sketch_events: invalid N or P")
+    ws = _workspace(nbytes, dev) if workspace is None else workspace
+    _check(_lib().srt3d_sketch_events(pp, ps, N, P, T, m, _dev(table, torch.float32, "table"),
+                                      _dev(z, torch.float32, "z"), _dev(n, torch.int32, "n"), _ptr(acc), _ptr(nacc),
+                                      _ptr(err), _ptr(ws), ws.numel(), _stream(dev)), "srt3d_sketch_events")
     return z, n
 
 

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsrt3d.so")
 OBJ = os.path.join(ROOT, "_build")
-SOURCES = ["sketch.hip", "binned.hip", "hist.hip", "srt3d.hip", "api.cpp"]
+SOURCES = ["sketch.hip", "binned.hip", "events.hip", "hist.hip", "srt3d.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -51,6 +51,10 @@ hipError_t launch_sketch_photons(const int32_t* stamps, int64_t N, const int64_t
 hipError_t launch_sketch_binned(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T,
                                 int m, const float2* table, float* z, int32_t* n, double* acc,
                                 int64_t* nacc, int32_t* err, hipStream_t s);
+size_t events_ws_bytes(int64_t N, int P);
+hipError_t launch_sketch_events(const int32_t* pix, const int32_t* stamps, int64_t N, int P, int T, int m,
+                                const float2* table, float* z, int32_t* n, double* acc, int64_t* nacc, int32_t* err,
+                                void* ws, hipStream_t s);
 hipError_t launch_hist_prepare(int T, int m, int precision, void* ws, hipStream_t s);
 hipError_t launch_sketch_hist(const uint16_t* hist, int P, int T, int m, int precision, const void* ws,
                               float* z, int32_t* n, hipStream_t s);

@@ -62,6 +62,13 @@ def test_workspace_queries(lib):
     assert lib.srt3d_init_workspace_bytes(ctypes.byref(p)) == 4096 * 4 + 256 + 2 * 2 * 64 * 4 + 2 * 16 * 4
     p.K_max = 4
     assert lib.srt3d_init_workspace_bytes(ctypes.byref(p)) == 0
+    # event streams: per-pixel int32 counts, int64 block sums (1024 counts a block), int64
+    # offsets [P + 1] and the grouped int32 stamps, each rounded up to 256 bytes
+    up = lambda b: (b + 255) // 256 * 256
+    assert lib.srt3d_sketch_events_workspace_bytes(1000, 3000) == up(4 * 3000) + up(8 * 3) + up(8 * 3001) + up(4000)
+    assert lib.srt3d_sketch_events_workspace_bytes(0, 1) == up(4) + up(8) + up(16) + up(4)
+    assert lib.srt3d_sketch_events_workspace_bytes(-1, 10) == 0
+    assert lib.srt3d_sketch_events_workspace_bytes(10, 0) == 0
 
 
 def test_invalid_arguments_rejected_on_host(lib):
@@ -82,6 +89,18 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.srt3d_sketch_binned(fake, 10, fake, 4, 1024, 4, None, fake, fake, None, None, None, None) == -1
     assert lib.srt3d_sketch_binned(fake, 10, fake, 4, 1024, 4, fake, fake, fake, fake, None, None, None) == -1
     assert lib.srt3d_phase_table(1, fake, None) == -1
+    # event streams: P < 1, m > T/2, NULL pixels with events, NULL workspace, misaligned or too
+    # small workspace
+    ws = VP(0x10000)
+    assert lib.srt3d_sketch_events(fake, fake, 10, 0, 1024, 4, fake, fake, fake, None, None, None, ws, 1 << 20, None) == -1
+    assert lib.srt3d_sketch_events(fake, fake, 10, 4, 1024, 513, fake, fake, fake, None, None, None, ws, 1 << 20,
+                                   None) == -1
+    assert lib.srt3d_sketch_events(None, fake, 10, 4, 1024, 4, fake, fake, fake, None, None, None, ws, 1 << 20, None) == -1
+    assert lib.srt3d_sketch_events(fake, fake, 10, 4, 1024, 4, fake, fake, fake, None, None, None, None, 1 << 20,
+                                   None) == -1
+    assert lib.srt3d_sketch_events(fake, fake, 10, 4, 1024, 4, fake, fake, fake, None, None, None, VP(0x10010),
+                                   1 << 20, None) == -1
+    assert lib.srt3d_sketch_events(fake, fake, 10, 4, 1024, 4, fake, fake, fake, None, None, None, ws, 16, None) == -2
     # histogram: T not a multiple of 32, m > 32, bad precision, misaligned pointer, small workspace
     assert lib.srt3d_hist_prepare(1000, 4, 0, fake, 1 << 20, None) == -1
     assert lib.srt3d_hist_prepare(1024, 4, 0, fake, 16, None) == -2
