@@ -302,7 +302,28 @@ def main():
     e_o[1].record(stream)
     torch.cuda.synchronize()
     other_ms = e_o[0].elapsed_time(e_o[1]) / 3
-    del z2, n2
+
+    # the same photons as an arrival-order event stream (pixel, stamp) in random order, sketched
+    # by srt3d_sketch_events (grouped on the device, then sketched); outside the timed steps
+    counts = frame.offsets[1:] - frame.offsets[:-1]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(spec.seed)
+    order = torch.randperm(N, device=dev, generator=gen)
+    ev_pix = torch.repeat_interleave(torch.arange(P, device=dev, dtype=torch.int32), counts)[order].contiguous()
+    ev_st = frame.stamps[order].contiguous()
+    del order
+    ev_ws = srt.events_workspace(N, P, dev)
+    srt.sketch_events(ev_pix, ev_st, P, T, m, z=z2, n=n2, table=table, workspace=ev_ws)
+    e_v = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e_v[0].record(stream)
+    for _ in range(3):
+        srt.sketch_events(ev_pix, ev_st, P, T, m, z=z2, n=n2, table=table, workspace=ev_ws)
+    e_v[1].record(stream)
+    torch.cuda.synchronize()
+    ev_ms = e_v[0].elapsed_time(e_v[1]) / 3
+    ev_same = bool(torch.equal(n2, n)) and (args.sketch != "binned" or bool(torch.equal(z2, z)))
+    ev_alg = 8.0 * N + 8.0 * m * P + 4.0 * P          # events in, sketch + counts out
+    del z2, n2, ev_pix, ev_st, ev_ws
     res = {
         "metric": METRIC,
         "value": args.steps / wall,
@@ -323,6 +344,9 @@ def main():
         "sketch_photons_per_s": N / (sk_ms.mean() * 1e-3),
         "sketch_method": args.sketch,
         "other_sketch": {"method": other, "ms": other_ms, "photons_per_s": N / (other_ms * 1e-3)},
+        "event_stream_sketch": {"ms": ev_ms, "events_per_s": N / (ev_ms * 1e-3),
+                                "hbm_frac": ev_alg / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                "algorithmic_bytes": ev_alg, "same_as_step_sketch": ev_same},
         "sketch_ms": {"mean": float(sk_ms.mean()), "p50": float(np.percentile(sk_ms, 50)),
                       "p99": float(np.percentile(sk_ms, 99))},
         "srt3d_ms": {"mean": float(rc_ms.mean()), "p50": float(np.percentile(rc_ms, 50)),

@@ -12,6 +12,7 @@ from ._lib import (  # noqa: F401
     Reconstructor,
     SRT3DError,
     cached_phase_table,
+    events_workspace,
     hist_workspace,
     phase_indices,
     phase_table,

@@ -167,6 +167,14 @@ def sketch(stamps: torch.Tensor, offsets: torch.Tensor, T: int, m: int, *, acc=N
     return z, n
 
 
+def events_workspace(N: int, P: int, device) -> torch.Tensor:
+    """A workspace for srt3d_sketch_events on N events and P pixels (reusable across calls)."""
+    nbytes = _lib().srt3d_sketch_events_workspace_bytes(int(N), int(P))
+    if nbytes == 0:
+        raise ValueError("sketch_events: invalid N or P")
+    return _workspace(nbytes, torch.device(device))
+
+
 def sketch_events(pix: torch.Tensor, stamps: torch.Tensor, P: int, T: int, m: int, *, acc=None, nacc=None,
                   err=None, z=None, n=None, table=None, workspace=None):
     """Sketch of an arrival-order event stream (srt3d_sketch_events): event e adds
@@ -188,13 +196,13 @@ def sketch_events(pix: torch.Tensor, stamps: torch.Tensor, P: int, T: int, m: in
         if not (2 <= T and T * 8 <= 65536):
             raise ValueError("sketch_events: invalid T")
         table = cached_phase_table(T, dev)
-    nbytes = _lib().srt3d_sketch_events_workspace_bytes(N, P)
-    if nbytes == 0:
-        raise ValueError("sketch_events: invalid N or P")
-    ws = _workspace(nbytes, dev) if workspace is None else workspace
+    if workspace is None:
+        workspace = events_workspace(N, P, dev)
+    _dev(workspace, torch.uint8, "workspace")
     _check(_lib().srt3d_sketch_events(pp, ps, N, P, T, m, _dev(table, torch.float32, "table"),
                                       _dev(z, torch.float32, "z"), _dev(n, torch.int32, "n"), _ptr(acc), _ptr(nacc),
-                                      _ptr(err), _ptr(ws), ws.numel(), _stream(dev)), "srt3d_sketch_events")
+                                      _ptr(err), _ptr(workspace), workspace.numel(), _stream(dev)),
+           "srt3d_sketch_events")
     return z, n
 
 
