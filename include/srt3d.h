@@ -158,18 +158,21 @@ int srt3d_sketch_binned(const int32_t* d_stamps, int64_t N, const int64_t* d_off
 /* ---------------------------------------------------------------------------------------
  * Sketch of an arrival-order event stream -- Section 2 (the sketch is updated online as each
  * photon arrives) and eq. (3): event e = (d_pix[e], d_stamps[e]) adds exp(i w_l x_e) to its
- * pixel.  The stream is grouped by pixel on the device (counting sort into d_ws) and sketched
- * as by srt3d_sketch_binned (m <= 32) or srt3d_sketch (m > 32); with the binned pass the result
- * does not depend on the order of the events (integer histograms).  Six kernel launches.
+ * pixel.  The stream is grouped by pixel on the device (a two-level counting sort, by
+ * buckets of consecutive pixels and then by pixel, into d_ws) and sketched as by
+ * srt3d_sketch_binned (m <= 32) or srt3d_sketch (m > 32); with the binned pass the result does
+ * not depend on the order of the events (integer histograms).  Six kernel launches.
  *   d_pix     int32 [N] pixel index of each event; events with an index outside [0, P) are
  *             dropped and counted in d_err[1]
- *   d_stamps  int32 [N] time stamps; stamps outside [0, T) are folded mod T and counted in
- *             d_err[0]
+ *   d_stamps  int32 [N] time stamps; stamps outside [0, T) of kept events are folded mod T
+ *             and counted in d_err[0]
  *   d_ws      workspace of srt3d_sketch_events_workspace_bytes(N, P) bytes, 256-byte aligned
- *             (per-pixel counts, CSR offsets, the grouped stamps); overwritten by each call
+ *             (bucket tables, CSR offsets, the bucket-grouped and the pixel-grouped stream, about
+ *             8 N + 8 P bytes); overwritten by each call
  *   d_table, d_z, d_n, d_acc, d_nacc, d_err: as srt3d_sketch
- * Constraints: as srt3d_sketch.  srt3d_sketch_events_workspace_bytes returns 0 for N < 0 or
- * P < 1; a smaller workspace gives SRT3D_ENOMEM.
+ * Constraints: as srt3d_sketch, and 0 <= N <= 2^31 - 1, 1 <= P <= 2^30 (longer streams are
+ * given in parts with d_acc / d_nacc).  srt3d_sketch_events_workspace_bytes returns 0 outside
+ * these; a smaller workspace gives SRT3D_ENOMEM.
  * ------------------------------------------------------------------------------------- */
 size_t srt3d_sketch_events_workspace_bytes(int64_t N, int32_t P);
 int srt3d_sketch_events(const int32_t* d_pix, const int32_t* d_stamps, int64_t N, int32_t P,

@@ -83,15 +83,19 @@ int srt3d_sketch_binned(const int32_t* d_stamps, int64_t N, const int64_t* d_off
                                            d_z, d_n, d_acc, d_nacc, d_err, as_stream(stream)));
 }
 
+namespace {
+bool events_dims_ok(int64_t N, int32_t P) { return N >= 0 && N <= INT32_MAX && P >= 1 && P <= (1 << 30); }
+}  // namespace
+
 size_t srt3d_sketch_events_workspace_bytes(int64_t N, int32_t P) {
-    if (N < 0 || P < 1) return 0;
+    if (!events_dims_ok(N, P)) return 0;
     return events_ws_bytes(N, P);
 }
 
 int srt3d_sketch_events(const int32_t* d_pix, const int32_t* d_stamps, int64_t N, int32_t P, int32_t T, int32_t m,
                         const float* d_table, float* d_z, int32_t* d_n, double* d_acc, int64_t* d_nacc,
                         int32_t* d_err, void* d_ws, size_t ws_bytes, void* stream) {
-    if (P < 1 || N < 0 || !sketch_dims_ok(T, m)) return SRT3D_EINVAL;
+    if (!events_dims_ok(N, P) || !sketch_dims_ok(T, m)) return SRT3D_EINVAL;
     if (((!d_pix || !d_stamps) && N > 0) || !d_table || !d_z || !d_n || !d_ws) return SRT3D_EINVAL;
     if ((d_acc == nullptr) != (d_nacc == nullptr)) return SRT3D_EINVAL;
     if (!aligned(d_table, 8) || !aligned(d_z, 8) || !aligned(d_ws, 256)) return SRT3D_EINVAL;

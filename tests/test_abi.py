@@ -62,13 +62,21 @@ def test_workspace_queries(lib):
     assert lib.srt3d_init_workspace_bytes(ctypes.byref(p)) == 4096 * 4 + 256 + 2 * 2 * 64 * 4 + 2 * 16 * 4
     p.K_max = 4
     assert lib.srt3d_init_workspace_bytes(ctypes.byref(p)) == 0
-    # event streams: per-pixel int32 counts, int64 block sums (1024 counts a block), int64
-    # offsets [P + 1] and the grouped int32 stamps, each rounded up to 256 bytes
+    # event streams: G = min(ceil(N / 8192), 512) stream chunks, NB buckets of W pixels (W the
+    # smaller of 2^ceil(log2(P) / 2) and 2^ceil(log2(ceil(P / 512)))); an int32 [NB][G] table,
+    # int64 [NB + 1] bucket slots, int64 [P + 1] offsets and two int32 [N] streams, each rounded
+    # up to 256 bytes
     up = lambda b: (b + 255) // 256 * 256
-    assert lib.srt3d_sketch_events_workspace_bytes(1000, 3000) == up(4 * 3000) + up(8 * 3) + up(8 * 3001) + up(4000)
-    assert lib.srt3d_sketch_events_workspace_bytes(0, 1) == up(4) + up(8) + up(16) + up(4)
+    ws = lambda N, P, G, NB: up(4 * NB * G) + up(8 * (NB + 1)) + up(8 * (P + 1)) + 2 * up(4 * max(N, 1))
+    assert lib.srt3d_sketch_events_workspace_bytes(1000, 3000) == ws(1000, 3000, 1, 375)        # W = 8
+    assert lib.srt3d_sketch_events_workspace_bytes(0, 1) == ws(0, 1, 1, 1)
+    assert lib.srt3d_sketch_events_workspace_bytes(1 << 20, 1000) == ws(1 << 20, 1000, 128, 500)  # W = 2
+    assert lib.srt3d_sketch_events_workspace_bytes(65_533_692, 65536) == ws(65_533_692, 65536, 512, 512)
+    assert lib.srt3d_sketch_events_workspace_bytes(100, 2**21 + 1) == ws(100, 2**21 + 1, 1, 1025)  # W = 2048
     assert lib.srt3d_sketch_events_workspace_bytes(-1, 10) == 0
     assert lib.srt3d_sketch_events_workspace_bytes(10, 0) == 0
+    assert lib.srt3d_sketch_events_workspace_bytes(2**31, 10) == 0
+    assert lib.srt3d_sketch_events_workspace_bytes(10, 2**30 + 1) == 0
 
 
 def test_invalid_arguments_rejected_on_host(lib):
@@ -90,7 +98,7 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.srt3d_sketch_binned(fake, 10, fake, 4, 1024, 4, fake, fake, fake, fake, None, None, None) == -1
     assert lib.srt3d_phase_table(1, fake, None) == -1
     # event streams: P < 1, m > T/2, NULL pixels with events, NULL workspace, misaligned or too
-    # small workspace
+    # small workspace, N or P past the limits
     ws = VP(0x10000)
     assert lib.srt3d_sketch_events(fake, fake, 10, 0, 1024, 4, fake, fake, fake, None, None, None, ws, 1 << 20, None) == -1
     assert lib.srt3d_sketch_events(fake, fake, 10, 4, 1024, 513, fake, fake, fake, None, None, None, ws, 1 << 20,
@@ -101,6 +109,10 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.srt3d_sketch_events(fake, fake, 10, 4, 1024, 4, fake, fake, fake, None, None, None, VP(0x10010),
                                    1 << 20, None) == -1
     assert lib.srt3d_sketch_events(fake, fake, 10, 4, 1024, 4, fake, fake, fake, None, None, None, ws, 16, None) == -2
+    assert lib.srt3d_sketch_events(fake, fake, 2**31, 4, 1024, 4, fake, fake, fake, None, None, None, ws, 1 << 20,
+                                   None) == -1
+    assert lib.srt3d_sketch_events(fake, fake, 10, 2**30 + 1, 1024, 4, fake, fake, fake, None, None, None, ws,
+                                   1 << 20, None) == -1
     # histogram: T not a multiple of 32, m > 32, bad precision, misaligned pointer, small workspace
     assert lib.srt3d_hist_prepare(1000, 4, 0, fake, 1 << 20, None) == -1
     assert lib.srt3d_hist_prepare(1024, 4, 0, fake, 16, None) == -2

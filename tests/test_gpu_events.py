@@ -87,6 +87,47 @@ def test_events_outside_the_frame_and_folded_stamps():
     _check(pix, st, P, T, m, z, n, "bad events")
 
 
+def test_events_outside_the_frame_in_a_long_stream():
+    """A stream of several chunks (13 counting workgroups), with a share of events whose pixel
+    is outside the frame and stamps outside [0, T)."""
+    dev = device()
+    rng = np.random.default_rng(12)
+    P, T, m = 1000, 2048, 8
+    pix, st = _stream(rng, P, T, rng.integers(0, 200, P))
+    k = pix.size // 20
+    pix[:k] = np.where(rng.random(k) < 0.5, -1 - rng.integers(0, 50, k), P + rng.integers(0, 50, k))
+    st[k:2 * k] = rng.integers(-3 * T, 4 * T, k)
+    err = torch.zeros(2, dtype=torch.int32, device=dev)
+    _print_case(test="bad_events_long", N=pix.size)
+    z, n = srt.sketch_events(_to_dev(pix, dev), _to_dev(st, dev), P, T, m, err=err)
+    torch.cuda.synchronize()
+    _, _, dropped, folded = OS.sketch_event_sums(pix, st, P, T, m)
+    assert dropped == k
+    assert err.cpu().tolist() == [folded, dropped]
+    _check(pix, st, P, T, m, z, n, "bad events, long stream")
+
+
+def test_large_frame_with_wide_bucket_tables():
+    """2^21 + 1 pixels: 1025 buckets of 2048 pixels, past the small LDS tables of both grouping
+    levels; the result is the CSR pass's, bit for bit, and the oracle's."""
+    dev = device()
+    rng = np.random.default_rng(13)
+    P, T, m = 2**21 + 1, 1024, 4
+    counts = rng.integers(0, 2, P)
+    counts[-1] = 5                      # the one-pixel last bucket
+    pix, st = _stream(rng, P, T, counts)
+    _print_case(test="large_frame", P=P, N=pix.size)
+    z, n = srt.sketch_events(_to_dev(pix, dev), _to_dev(st, dev), P, T, m)
+    order = np.argsort(pix, kind="stable")
+    offsets = np.zeros(P + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(counts)
+    zc, nc = srt.sketch(_to_dev(st[order], dev), torch.from_numpy(offsets).to(dev), T, m, method="binned")
+    torch.cuda.synchronize()
+    assert torch.equal(n, nc)
+    assert torch.equal(z, zc)
+    _check(pix, st, P, T, m, z, n, "large frame")
+
+
 def test_empty_stream_and_single_events():
     dev = device()
     for pix, st, P in (([], [], 7), ([3], [17], 5), ([0, 0, 0], [1, 2, 3], 1)):
