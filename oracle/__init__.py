@@ -14,6 +14,8 @@ Modules
           sizes, data step, point-cloud and intensity denoisers, background,
           output); the parts the paper leaves open follow the readings listed
           in each function's docstring.
+  smle    the pixelwise sketched estimator (SRT3D's data steps alone, per-pixel
+          steps, several starts, the lowest loss kept): the comparison system.
 
 Parity status: every function is pinned by the `-m "not gpu"` tests in
 `tests/test_oracle_*.py` against closed forms, invariants or brute force.
