@@ -58,6 +58,7 @@ enum srt3d_stage {
 #define SRT3D_MAX_M_RECON 64   /* harmonics usable by init/iterate */
 #define SRT3D_MAX_K 3          /* surfaces per pixel */
 #define SRT3D_MAX_R 3          /* denoiser window radius */
+#define SRT3D_MAX_STARTS 64    /* starting points of srt3d_smle */
 #define SRT3D_NSCAL 8          /* floats in srt3d_state.scal */
 
 /*
@@ -240,6 +241,26 @@ int srt3d_reconstruct(const float* d_z, const int32_t* d_n, const double* d_irf,
                       int32_t irf_len, int32_t irf_origin, const srt3d_params* p,
                       srt3d_state* st, float* d_depth, float* d_intensity, uint8_t* d_active,
                       float* d_bg, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Pixelwise sketched estimator -- the comparison system of Sections 1 and 4 (SMLE): each
+ * pixel's loss n ||z - Phi(theta)||^2 (eq. 6 with W = I) minimised on its own, with no
+ * spatial prior, from `starts` starting points, keeping the lowest loss.  srt3d_smle runs
+ * srt3d_init (its points are start 0), then for start s = 1..starts-1 puts point k at
+ * (s T / starts + k T / K_max) mod T with the single-atom least-squares amplitude
+ * max(0, Re sum_l conj(hhat_l e^{i w_l t_k}) z_l / sum_l |hhat_l|^2), every point active where
+ * n > 0 and alpha projected onto {alpha >= 0, sum alpha <= 1}; each start takes p->iters data
+ * steps (srt3d_stage DATA with per-pixel step sizes: the frame's steps scaled by n_max / n;
+ * no point is removed).  All starts run in one kernel launch after the initialisation.
+ *   d_z, d_n, d_irf, irf_len, irf_origin, p, st, d_ws, ws_bytes: as srt3d_init (workspace of
+ *              srt3d_init_workspace_bytes(p) bytes)
+ *   starts     1 <= starts <= SRT3D_MAX_STARTS
+ *   d_loss     float32 [P]: the chosen start's loss (the earliest start on ties)
+ * On return st->cur = 1 holds the chosen points; srt3d_finalize gives the outputs.
+ * ------------------------------------------------------------------------------------- */
+int srt3d_smle(const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len,
+               int32_t irf_origin, const srt3d_params* p, int32_t starts, srt3d_state* st,
+               float* d_loss, void* d_ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------
  * Inspection entry point used to check the exact part of the sketch.

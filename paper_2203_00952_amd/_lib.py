@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsrt3d.so")
 SRT3D_OK, SRT3D_EINVAL, SRT3D_ENOMEM, SRT3D_EDEVICE = 0, -1, -2, -3
 PRECISIONS = {"fp32": 0, "fp16x2": 1, "bf16x3": 2}
 STAGES = {"data": 0, "depth": 1, "intensity": 2}
-MAX_M_RECON, MAX_K, MAX_R, NSCAL = 64, 3, 3, 8
+MAX_M_RECON, MAX_K, MAX_R, NSCAL, MAX_STARTS = 64, 3, 3, 8, 64
 
 
 class SRT3DError(RuntimeError):
@@ -55,6 +55,8 @@ _SIGS = {
     "srt3d_init_workspace_bytes": (_SZ, [ctypes.POINTER(_Params)]),
     "srt3d_init": (_I32, [_VP, _VP, _VP, _I32, _I32, ctypes.POINTER(_Params), ctypes.POINTER(_State), _VP, _SZ,
                           _VP]),
+    "srt3d_smle": (_I32, [_VP, _VP, _VP, _I32, _I32, ctypes.POINTER(_Params), _I32, ctypes.POINTER(_State), _VP,
+                          _VP, _SZ, _VP]),
     "srt3d_step": (_I32, [ctypes.POINTER(_State), _VP, _VP, ctypes.POINTER(_Params), _I32, _VP]),
     "srt3d_iterate": (_I32, [ctypes.POINTER(_State), _VP, _VP, ctypes.POINTER(_Params), _I32, _VP]),
     "srt3d_finalize": (_I32, [ctypes.POINTER(_State), _VP, ctypes.POINTER(_Params), _VP, _VP, _VP, _VP, _VP]),
@@ -326,6 +328,20 @@ class Reconstructor:
         _check(_lib().srt3d_init(_ptr(z), _ptr(n), _ptr(irf), irf.numel(), origin, ctypes.byref(self._cp),
                                  ctypes.byref(self._st), _ptr(self.ws), self.ws.numel(), _stream(self.device)),
                "srt3d_init")
+
+    def smle(self, z, n, irf: torch.Tensor, origin: int, starts: int, loss=None):
+        """Pixelwise sketched estimator (srt3d_smle): SRT3D's data steps alone from `starts`
+        starting points per pixel, the lowest loss kept.  Leaves the chosen points as the
+        current state (finalize gives the outputs) and returns the per-pixel loss [P]."""
+        self._zn(z, n)
+        _dev(irf, torch.float64, "irf")
+        if loss is None:
+            loss = torch.empty(self.p.P, dtype=torch.float32, device=self.device)
+        _dev(loss, torch.float32, "loss")
+        _check(_lib().srt3d_smle(_ptr(z), _ptr(n), _ptr(irf), irf.numel(), origin, ctypes.byref(self._cp), starts,
+                                 ctypes.byref(self._st), _ptr(loss), _ptr(self.ws), self.ws.numel(),
+                                 _stream(self.device)), "srt3d_smle")
+        return loss
 
     def step(self, stage: str, z, n):
         self._zn(z, n)

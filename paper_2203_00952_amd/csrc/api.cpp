@@ -145,6 +145,25 @@ int srt3d_init(const float* d_z, const int32_t* d_n, const double* d_irf, int32_
     return dev_status(launch_init(d_z, d_n, d_irf, irf_len, irf_origin, *p, *st, d_ws, as_stream(stream)));
 }
 
+int srt3d_smle(const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len, int32_t irf_origin,
+               const srt3d_params* p, int32_t starts, srt3d_state* st, float* d_loss, void* d_ws, size_t ws_bytes,
+               void* stream) {
+    int rc = check_params(p);
+    if (rc != SRT3D_OK) return rc;
+    if ((rc = check_state(st)) != SRT3D_OK) return rc;
+    if (starts < 1 || starts > SRT3D_MAX_STARTS || !d_loss) return SRT3D_EINVAL;
+    if (!d_z || !d_n || !d_irf || !d_ws || irf_len < 1 || irf_origin < 0 || irf_origin >= irf_len)
+        return SRT3D_EINVAL;
+    if (!aligned(d_ws, 16) || !aligned(d_z, 8) || !aligned(st->hhat, 8) || !aligned(d_loss, 4)) return SRT3D_EINVAL;
+    if (ws_bytes < init_ws_bytes(*p)) return SRT3D_ENOMEM;
+    const hipStream_t s = as_stream(stream);
+    st->cur = 0;
+    if (launch_init(d_z, d_n, d_irf, irf_len, irf_origin, *p, *st, d_ws, s) != hipSuccess) return SRT3D_EDEVICE;
+    if (launch_smle(*p, d_z, d_n, *st, starts, 0, 1, d_loss, s) != hipSuccess) return SRT3D_EDEVICE;
+    st->cur = 1;
+    return SRT3D_OK;
+}
+
 int srt3d_step(srt3d_state* st, const float* d_z, const int32_t* d_n, const srt3d_params* p, int32_t stage,
                void* stream) {
     int rc = check_params(p);

@@ -64,6 +64,8 @@ hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int 
                        const srt3d_params& p, const srt3d_state& st, void* ws, hipStream_t s);
 hipError_t launch_data_step(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st,
                             int cur, hipStream_t s);
+hipError_t launch_smle(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st, int starts,
+                       int src, int dst, float* loss, hipStream_t s);
 hipError_t launch_depth_denoise(const srt3d_params& p, const srt3d_state& st, int src, int dst, hipStream_t s);
 hipError_t launch_intensity_denoise(const srt3d_params& p, const int32_t* n, const srt3d_state& st, int src,
                                     int dst, hipStream_t s);

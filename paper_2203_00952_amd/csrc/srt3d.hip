@@ -500,6 +500,7 @@ __device__ __forceinline__ float quad_first(float v) { return quad_dpp<0x00>(v);
 // Partial gradient sums are combined over the four lanes, which then apply identical updates.
 constexpr int kLanesPerPixel = 4;
 constexpr int kMaxSlice = (SRT3D_MAX_M_RECON + kLanesPerPixel - 1) / kLanesPerPixel;   // harmonics per lane
+constexpr int kPrefetchSlice = 8;   // slices of up to 8 harmonics (m <= 32) are prefetched into registers
 
 // Where a lane's sketch values come from: the pixel's row in global memory, or registers filled
 // earlier (the fused iteration prefetches them at its start).  Same values either way.
@@ -621,6 +622,154 @@ __global__ __launch_bounds__(256) void data_step_kernel(IterArgs A, const float*
     for (int k = 0; k < K; ++k) {
         t[(int64_t)pix * K + k] = tk[k];
         alpha[(int64_t)pix * K + k] = ak[k];
+    }
+}
+
+// ----------------------------------------------------------------------------- pixelwise estimator
+// The comparison estimator of Sections 1 and 4 (SMLE): each pixel's sketched loss minimised on
+// its own -- the data steps above with no denoisers -- from `starts` starting points, keeping
+// the lowest loss.  Start 0 is the SRT3D initialisation; start s >= 1 puts point k at
+// (s T / S + k T / K) mod T with its single-atom least-squares amplitude, all points active
+// where n > 0, and alpha projected onto the constraint set.  Steps are per pixel: the pixel
+// takes the frame's step sizes as if it had n_max photons.  Points are never removed.
+
+// Sum over the four lanes of a pixel's quad (identical on all four).
+__device__ __forceinline__ float quad_sum(float v) {
+    v += quad_xor1(v);
+    v += quad_xor2(v);
+    return v;
+}
+
+template <int K, int MS, class Src>
+__device__ __forceinline__ void smle_start(const Src& src, int lo, int hi, int s, int S, int T, float e2, bool has,
+                                           float* tk, float* ak, bool* on) {
+    const float Tf = (float)T, invT = 1.0f / Tf, twoinvT = 2.0f / Tf;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double t = fmod((double)s * T / S + (double)k * T / K, (double)T);
+        tk[k] = wrap_t((float)t, Tf);
+        float c = 0.f;
+#pragma unroll
+        for (int j = 0; j < MS; ++j) {
+            const int l0 = lo + j;
+            if (l0 >= hi) break;
+            const float2 g = cmul(src.h(l0), phasor(l0 + 1, tk[k], T, invT, twoinvT));
+            const float2 zl = src.z(l0, j);
+            c += g.x * zl.x + g.y * zl.y;
+        }
+        c = quad_sum(c);
+        ak[k] = e2 > 0.f ? fmaxf(0.f, c / e2) : 0.f;
+        on[k] = has;
+    }
+    project_capped_simplex<K>(ak, on);
+}
+
+// Sum over the pixel's harmonics of |Phi_l - z_l|^2 (active points only).
+template <int K, int MS, class Src>
+__device__ __forceinline__ float smle_residual(const Src& src, int lo, int hi, int T, const float* tk, const float* ak,
+                                               const bool* on) {
+    const float Tf = (float)T, invT = 1.0f / Tf, twoinvT = 2.0f / Tf;
+    float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < MS; ++j) {
+        const int l0 = lo + j;
+        if (l0 >= hi) break;
+        const float2 h = src.h(l0);
+        const float2 zl = src.z(l0, j);
+        float2 e = make_float2(-zl.x, -zl.y);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!on[k]) continue;
+            const float2 g = cmul(h, phasor(l0 + 1, tk[k], T, invT, twoinvT));
+            e.x += ak[k] * g.x;
+            e.y += ak[k] * g.y;
+        }
+        acc += e.x * e.x + e.y * e.y;
+    }
+    return quad_sum(acc);
+}
+
+template <int K, int MS, class Src>
+__device__ __forceinline__ void smle_pixel(const Src& src, int pix, int sub, const IterArgs& A, int starts, int iters,
+                                           const int32_t* __restrict__ n, const float* __restrict__ scal,
+                                           const float* __restrict__ t0, const float* __restrict__ a0,
+                                           const uint8_t* __restrict__ act0, float* __restrict__ t_out,
+                                           float* __restrict__ a_out, uint8_t* __restrict__ act_out,
+                                           float* __restrict__ loss_out) {
+    const int lo = (sub * A.m) / kLanesPerPixel, hi = ((sub + 1) * A.m) / kLanesPerPixel;
+    const int np = n[pix];
+    const float nq = (float)np, nstep = np > 0 ? scal[0] : 0.f;
+    float tb[K], ab[K], best = 0.f;
+    bool ob[K];
+    for (int s = 0; s < starts; ++s) {
+        float tk[K], ak[K];
+        bool on[K];
+        if (s == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int64_t q = (int64_t)pix * K + k;
+                tk[k] = t0[q];
+                ak[k] = a0[q];
+                on[k] = act0[q] != 0;
+            }
+        } else {
+            smle_start<K, MS>(src, lo, hi, s, starts, A.T, scal[4], np > 0, tk, ak, on);
+        }
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k) any |= on[k];
+        if (any)
+            for (int it = 0; it < iters; ++it) data_point<K, MS>(src, sub, A.m, A.T, nstep, scal[1], scal[2], tk, ak, on);
+        const float L = nq * smle_residual<K, MS>(src, lo, hi, A.T, tk, ak, on);
+        if (s == 0 || L < best) {
+            best = L;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                tb[k] = tk[k];
+                ab[k] = ak[k];
+                ob[k] = on[k];
+            }
+        }
+    }
+    if (sub != 0) return;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t q = (int64_t)pix * K + k;
+        t_out[q] = tb[k];
+        a_out[q] = ab[k];
+        act_out[q] = ob[k] ? 1 : 0;
+    }
+    loss_out[pix] = best;
+}
+
+// One launch for all starts and steps: four lanes per pixel, the pixel's sketch slice in
+// registers when m <= 32.
+template <int K, bool PREFETCH>
+__global__ __launch_bounds__(256) void smle_kernel(IterArgs A, int starts, int iters, const float* __restrict__ z,
+                                                   const int32_t* __restrict__ n, const float* __restrict__ hhat,
+                                                   const float* __restrict__ scal, const float* __restrict__ t0,
+                                                   const float* __restrict__ a0, const uint8_t* __restrict__ act0,
+                                                   float* __restrict__ t_out, float* __restrict__ a_out,
+                                                   uint8_t* __restrict__ act_out, float* __restrict__ loss_out) {
+    __shared__ float2 s_h[SRT3D_MAX_M_RECON];
+    for (int l = threadIdx.x; l < A.m; l += blockDim.x) s_h[l] = reinterpret_cast<const float2*>(hhat)[l];
+    __syncthreads();
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int pix = gid / kLanesPerPixel, sub = gid % kLanesPerPixel;
+    if (pix >= A.P) return;                      // the four lanes of a pixel leave together
+    const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * A.m);
+    if constexpr (PREFETCH) {
+        const int lo = (sub * A.m) / kLanesPerPixel, hi = ((sub + 1) * A.m) / kLanesPerPixel;
+        float2 zr[kPrefetchSlice];
+#pragma unroll
+        for (int j = 0; j < kPrefetchSlice; ++j) zr[j] = zp[lo + j < hi ? lo + j : lo];
+        const RegSketch<kPrefetchSlice> src{zr, s_h};
+        smle_pixel<K, kPrefetchSlice>(src, pix, sub, A, starts, iters, n, scal, t0, a0, act0, t_out, a_out, act_out,
+                                      loss_out);
+    } else {
+        const GlobalSketch src{zp, s_h};
+        smle_pixel<K, kMaxSlice>(src, pix, sub, A, starts, iters, n, scal, t0, a0, act0, t_out, a_out, act_out,
+                                 loss_out);
     }
 }
 
@@ -963,7 +1112,6 @@ constexpr int kIterTY = 8, kIterTX = 16;
 constexpr int kIterPix = kIterTY * kIterTX;
 constexpr int kIterThreads = kIterPix * kLanesPerPixel;
 
-constexpr int kPrefetchSlice = 8;   // the fused data step prefetches slices of up to 8 harmonics (m <= 32)
 
 template <int K, int R, bool DS_NEXT, bool DD_DONE>
 __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
@@ -1279,6 +1427,23 @@ hipError_t launch_data_step(const srt3d_params& p, const float* z, const int32_t
     const dim3 grid((unsigned)(((int64_t)A.P * kLanesPerPixel + 255) / 256));
     SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((data_step_kernel<KK>), grid, dim3(256), 0, s, A, z, n, st.hhat, st.scal, st.t[cur], st.alpha[cur],
                                            st.active[cur]));
+    return hipGetLastError();
+}
+
+hipError_t launch_smle(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st, int starts,
+                       int src, int dst, float* loss, hipStream_t s) {
+    const IterArgs A = make_args(p);
+    const dim3 grid((unsigned)(((int64_t)A.P * kLanesPerPixel + 255) / 256));
+    const bool pref = p.m <= kLanesPerPixel * kPrefetchSlice;
+    if (pref) {
+        SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((smle_kernel<KK, true>), grid, dim3(256), 0, s, A, starts, p.iters, z, n,
+                                               st.hhat, st.scal, st.t[src], st.alpha[src], st.active[src], st.t[dst],
+                                               st.alpha[dst], st.active[dst], loss));
+    } else {
+        SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((smle_kernel<KK, false>), grid, dim3(256), 0, s, A, starts, p.iters, z, n,
+                                               st.hhat, st.scal, st.t[src], st.alpha[src], st.active[src], st.t[dst],
+                                               st.alpha[dst], st.active[dst], loss));
+    }
     return hipGetLastError();
 }
 

@@ -143,6 +143,11 @@ def test_invalid_reconstruction_arguments(lib):
     assert lib.srt3d_init(fake, fake, fake, 5, 5, *args[5:]) == -1            # origin outside irf
     assert lib.srt3d_init(fake, fake, fake, 0, 0, *args[5:]) == -1            # empty irf
     assert lib.srt3d_init(*args[:7], fake, 16, None) == -2                    # workspace too small
+    # pixelwise estimator: starts outside [1, 64], NULL loss, small workspace
+    for starts, loss in ((0, fake), (65, fake), (2, None)):
+        assert lib.srt3d_smle(fake, fake, fake, 5, 2, ctypes.byref(p), starts, ctypes.byref(st), loss, fake, 1 << 20,
+                              None) == -1
+    assert lib.srt3d_smle(fake, fake, fake, 5, 2, ctypes.byref(p), 2, ctypes.byref(st), fake, fake, 16, None) == -2
     st2 = L._State()
     ctypes.pointer(st2)[0] = st
     st2.cur = 2
