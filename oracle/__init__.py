@@ -16,6 +16,8 @@ Modules
           in each function's docstring.
   smle    the pixelwise sketched estimator (SRT3D's data steps alone, per-pixel
           steps, several starts, the lowest loss kept): the comparison system.
+  weighted  eq. (6) with W = Sigma^{-1}: the sketch covariance from the characteristic
+          function and a two-step weighted fit of each pixel.
 
 Parity status: every function is pinned by the `-m "not gpu"` tests in
 `tests/test_oracle_*.py` against closed forms, invariants or brute force.
