@@ -59,6 +59,8 @@ enum srt3d_stage {
 #define SRT3D_MAX_K 3          /* surfaces per pixel */
 #define SRT3D_MAX_R 3          /* denoiser window radius */
 #define SRT3D_MAX_STARTS 64    /* starting points of srt3d_smle */
+#define SRT3D_MAX_M_WEIGHTED 32 /* harmonics usable by srt3d_smle_weighted */
+#define SRT3D_MAX_WITERS 1000  /* weighted-fit iterations of srt3d_smle_weighted */
 #define SRT3D_NSCAL 8          /* floats in srt3d_state.scal */
 
 /*
@@ -261,6 +263,34 @@ int srt3d_reconstruct(const float* d_z, const int32_t* d_n, const double* d_irf,
 int srt3d_smle(const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len,
                int32_t irf_origin, const srt3d_params* p, int32_t starts, srt3d_state* st,
                float* d_loss, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Eq. (6) with the precision-matrix weighting W = Sigma^{-1} (Section 2, with eq. (5): the
+ * sketch is asymptotically normal with covariance Sigma / n), pixel by pixel, as a two-step
+ * estimator.  srt3d_smle_weighted runs srt3d_smle (starts, p->iters steps: theta_1), then for
+ * each pixel builds Sigma(theta_1), the covariance of the sketch's 2m real coordinates
+ * [cos w_l x, sin w_l x] under eq. (1)'s pmf, from the characteristic function at sums and
+ * differences of frequencies (eq. 4 at w_a +- w_b, so the impulse response's spectrum up to
+ * harmonic 2m), adds 1e-5 tr(Sigma) / (2m) to its diagonal, factors it (L L^T) and runs
+ * `witers` Levenberg-Marquardt steps on n ||L^{-1} [Re(z - Phi), Im(z - Phi)]||^2 over the
+ * active points (a step kept iff it lowers that loss; mu from 1e-3, / 10 on success down to
+ * 1e-7, * 10 on failure up to 1e7; alpha projected, t wrapped).  Points are neither added nor
+ * removed.  One wave per pixel.
+ *   arguments as srt3d_smle, plus witers (0 <= witers <= SRT3D_MAX_WITERS); the workspace is
+ *   srt3d_smle_weighted_workspace_bytes(p) bytes, 16-byte aligned
+ *   d_loss     float32 [P]: the weighted loss at the returned points
+ * Constraints: as srt3d_smle, and m <= SRT3D_MAX_M_WEIGHTED, 2 m < T.  On return
+ * st->cur = 1 holds the points.
+ * srt3d_weighted_fit: the second step alone, from the points of the current half (taken as
+ *   theta_1), in place; same workspace; st->cur is unchanged.
+ * ------------------------------------------------------------------------------------- */
+size_t srt3d_smle_weighted_workspace_bytes(const srt3d_params* p);
+int srt3d_weighted_fit(srt3d_state* st, const float* d_z, const int32_t* d_n, const double* d_irf,
+                       int32_t irf_len, int32_t irf_origin, const srt3d_params* p, int32_t witers,
+                       float* d_loss, void* d_ws, size_t ws_bytes, void* stream);
+int srt3d_smle_weighted(const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len,
+                        int32_t irf_origin, const srt3d_params* p, int32_t starts, int32_t witers,
+                        srt3d_state* st, float* d_loss, void* d_ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------
  * Inspection entry point used to check the exact part of the sketch.

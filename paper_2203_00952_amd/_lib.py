@@ -57,6 +57,11 @@ _SIGS = {
                           _VP]),
     "srt3d_smle": (_I32, [_VP, _VP, _VP, _I32, _I32, ctypes.POINTER(_Params), _I32, ctypes.POINTER(_State), _VP,
                           _VP, _SZ, _VP]),
+    "srt3d_smle_weighted_workspace_bytes": (_SZ, [ctypes.POINTER(_Params)]),
+    "srt3d_weighted_fit": (_I32, [ctypes.POINTER(_State), _VP, _VP, _VP, _I32, _I32, ctypes.POINTER(_Params), _I32,
+                                  _VP, _VP, _SZ, _VP]),
+    "srt3d_smle_weighted": (_I32, [_VP, _VP, _VP, _I32, _I32, ctypes.POINTER(_Params), _I32, _I32,
+                                   ctypes.POINTER(_State), _VP, _VP, _SZ, _VP]),
     "srt3d_step": (_I32, [ctypes.POINTER(_State), _VP, _VP, ctypes.POINTER(_Params), _I32, _VP]),
     "srt3d_iterate": (_I32, [ctypes.POINTER(_State), _VP, _VP, ctypes.POINTER(_Params), _I32, _VP]),
     "srt3d_finalize": (_I32, [ctypes.POINTER(_State), _VP, ctypes.POINTER(_Params), _VP, _VP, _VP, _VP, _VP]),
@@ -341,6 +346,43 @@ class Reconstructor:
         _check(_lib().srt3d_smle(_ptr(z), _ptr(n), _ptr(irf), irf.numel(), origin, ctypes.byref(self._cp), starts,
                                  ctypes.byref(self._st), _ptr(loss), _ptr(self.ws), self.ws.numel(),
                                  _stream(self.device)), "srt3d_smle")
+        return loss
+
+    def smle_weighted(self, z, n, irf: torch.Tensor, origin: int, starts: int, witers: int, loss=None):
+        """Eq. (6) with W = Sigma^{-1} as a two-step estimator (srt3d_smle_weighted): the
+        pixelwise W = I estimate, then `witers` weighted Levenberg-Marquardt steps from it.
+        Leaves the points as the current state and returns the weighted loss [P]."""
+        self._zn(z, n)
+        _dev(irf, torch.float64, "irf")
+        need = _lib().srt3d_smle_weighted_workspace_bytes(ctypes.byref(self._cp))
+        if need == 0:
+            raise ValueError("smle_weighted: needs m <= 32 and 2 m < T")
+        if self.ws.numel() < need:
+            self.ws = _workspace(need, self.device)
+        if loss is None:
+            loss = torch.empty(self.p.P, dtype=torch.float32, device=self.device)
+        _dev(loss, torch.float32, "loss")
+        _check(_lib().srt3d_smle_weighted(_ptr(z), _ptr(n), _ptr(irf), irf.numel(), origin, ctypes.byref(self._cp),
+                                          starts, witers, ctypes.byref(self._st), _ptr(loss), _ptr(self.ws),
+                                          self.ws.numel(), _stream(self.device)), "srt3d_smle_weighted")
+        return loss
+
+    def weighted_fit(self, z, n, irf: torch.Tensor, origin: int, witers: int, loss=None):
+        """The weighted second step alone (srt3d_weighted_fit), from the current points, in
+        place; returns the weighted loss [P]."""
+        self._zn(z, n)
+        _dev(irf, torch.float64, "irf")
+        need = _lib().srt3d_smle_weighted_workspace_bytes(ctypes.byref(self._cp))
+        if need == 0:
+            raise ValueError("weighted_fit: needs m <= 32 and 2 m < T")
+        if self.ws.numel() < need:
+            self.ws = _workspace(need, self.device)
+        if loss is None:
+            loss = torch.empty(self.p.P, dtype=torch.float32, device=self.device)
+        _dev(loss, torch.float32, "loss")
+        _check(_lib().srt3d_weighted_fit(ctypes.byref(self._st), _ptr(z), _ptr(n), _ptr(irf), irf.numel(), origin,
+                                         ctypes.byref(self._cp), witers, _ptr(loss), _ptr(self.ws), self.ws.numel(),
+                                         _stream(self.device)), "srt3d_weighted_fit")
         return loss
 
     def step(self, stage: str, z, n):

@@ -164,6 +164,57 @@ int srt3d_smle(const float* d_z, const int32_t* d_n, const double* d_irf, int32_
     return SRT3D_OK;
 }
 
+namespace {
+size_t smle_weighted_ws(const srt3d_params& p) {
+    return ((init_ws_bytes(p) + 255) & ~(size_t)255) + (size_t)2 * p.m * sizeof(float) * 2;
+}
+bool weighted_dims_ok(const srt3d_params* p) { return p->m <= SRT3D_MAX_M_WEIGHTED && 2 * p->m < p->T; }
+}  // namespace
+
+size_t srt3d_smle_weighted_workspace_bytes(const srt3d_params* p) {
+    if (check_params(p) != SRT3D_OK || !weighted_dims_ok(p)) return 0;
+    return smle_weighted_ws(*p);
+}
+
+int srt3d_weighted_fit(srt3d_state* st, const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len,
+                       int32_t irf_origin, const srt3d_params* p, int32_t witers, float* d_loss, void* d_ws,
+                       size_t ws_bytes, void* stream) {
+    int rc = check_params(p);
+    if (rc != SRT3D_OK) return rc;
+    if ((rc = check_state(st)) != SRT3D_OK) return rc;
+    if (!weighted_dims_ok(p) || witers < 0 || witers > SRT3D_MAX_WITERS || !d_loss) return SRT3D_EINVAL;
+    if (!d_z || !d_n || !d_irf || !d_ws || irf_len < 1 || irf_origin < 0 || irf_origin >= irf_len)
+        return SRT3D_EINVAL;
+    if (!aligned(d_ws, 16) || !aligned(d_z, 8) || !aligned(d_loss, 4)) return SRT3D_EINVAL;
+    if (ws_bytes < smle_weighted_ws(*p)) return SRT3D_ENOMEM;
+    void* spec = static_cast<char*>(d_ws) + ((init_ws_bytes(*p) + 255) & ~(size_t)255);
+    return dev_status(launch_wsmle(*p, d_irf, irf_len, irf_origin, d_z, d_n, *st, st->cur, witers, d_loss, spec,
+                                   as_stream(stream)));
+}
+
+int srt3d_smle_weighted(const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len,
+                        int32_t irf_origin, const srt3d_params* p, int32_t starts, int32_t witers, srt3d_state* st,
+                        float* d_loss, void* d_ws, size_t ws_bytes, void* stream) {
+    int rc = check_params(p);
+    if (rc != SRT3D_OK) return rc;
+    if ((rc = check_state(st)) != SRT3D_OK) return rc;
+    if (!weighted_dims_ok(p) || witers < 0 || witers > SRT3D_MAX_WITERS) return SRT3D_EINVAL;
+    if (starts < 1 || starts > SRT3D_MAX_STARTS || !d_loss) return SRT3D_EINVAL;
+    if (!d_z || !d_n || !d_irf || !d_ws || irf_len < 1 || irf_origin < 0 || irf_origin >= irf_len)
+        return SRT3D_EINVAL;
+    if (!aligned(d_ws, 16) || !aligned(d_z, 8) || !aligned(st->hhat, 8) || !aligned(d_loss, 4)) return SRT3D_EINVAL;
+    if (ws_bytes < smle_weighted_ws(*p)) return SRT3D_ENOMEM;
+    const hipStream_t s = as_stream(stream);
+    void* spec = static_cast<char*>(d_ws) + ((init_ws_bytes(*p) + 255) & ~(size_t)255);
+    st->cur = 0;
+    if (launch_init(d_z, d_n, d_irf, irf_len, irf_origin, *p, *st, d_ws, s) != hipSuccess) return SRT3D_EDEVICE;
+    if (launch_smle(*p, d_z, d_n, *st, starts, 0, 1, d_loss, s) != hipSuccess) return SRT3D_EDEVICE;
+    st->cur = 1;
+    if (launch_wsmle(*p, d_irf, irf_len, irf_origin, d_z, d_n, *st, 1, witers, d_loss, spec, s) != hipSuccess)
+        return SRT3D_EDEVICE;
+    return SRT3D_OK;
+}
+
 int srt3d_step(srt3d_state* st, const float* d_z, const int32_t* d_n, const srt3d_params* p, int32_t stage,
                void* stream) {
     int rc = check_params(p);

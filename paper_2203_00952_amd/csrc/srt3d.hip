@@ -773,6 +773,282 @@ __global__ __launch_bounds__(256) void smle_kernel(IterArgs A, int starts, int i
     }
 }
 
+// ----------------------------------------------------------------------------- precision weighting
+// Eq. (6) with W = Sigma^{-1}, pixel by pixel, as the second step after the pixelwise W = I
+// estimate theta_1.  Sigma is the covariance of the sketch's 2m real coordinates
+// [cos w_l x, sin w_l x] under pi_theta_1 (eq. 1), built from the characteristic function at
+// sums and differences of frequencies (eq. 4 at w_a +- w_b), ridged by 1e-5 tr(Sigma) / (2m),
+// factored once (L L^T) and held fixed; then Levenberg-Marquardt on the whitened residual
+// L^{-1} [Re(z - Phi), Im(z - Phi)] over the active points' (t_k, alpha_k), a step kept iff it
+// lowers n ||L^{-1} r||^2 (mu from 1e-3, / 10 on success down to 1e-7, * 10 on failure up to
+// 1e7), alpha projected onto the constraint set, t wrapped.
+//
+// One wave per pixel; lane i owns row i of Sigma, then of L (row-oriented Cholesky with the
+// pivot column broadcast by readlane), and entry i of every whitened vector (forward
+// substitution one column at a time).  M2 >= 2m is the row length; rows 2m..M2-1 are identity.
+
+// hhat_l for l = 1..J (J <= 2 SRT3D_MAX_M_RECON), one harmonic per wave, the FP64 sums of the
+// frame setup.
+__global__ __launch_bounds__(1024) void spectrum_kernel(const double* __restrict__ irf, int irf_len, int origin,
+                                                        int T, int J, float2* __restrict__ out) {
+    __shared__ double s_H;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (wv == 0) {
+        double h0 = 0;
+        for (int i = lane; i < irf_len; i += 64) h0 += irf[i];
+        h0 = wave_sum_d(h0);
+        if (lane == 0) s_H = h0;
+    }
+    __syncthreads();
+    const double H = s_H;
+    for (int l = 1 + wv; l <= J; l += blockDim.x >> 6) {
+        double re = 0, im = 0;
+        for (int i = lane; i < irf_len; i += 64) {
+            int k = (int)(((int64_t)l * (i - origin)) % T);
+            if (k < 0) k += T;
+            double sn, cs;
+            sincospi(2.0 * (double)k / (double)T, &sn, &cs);
+            re += irf[i] * cs;
+            im += irf[i] * sn;
+        }
+        re = wave_sum_d(re) / H;
+        im = wave_sum_d(im) / H;
+        if (lane == 0) out[l - 1] = make_float2((float)re, (float)im);
+    }
+}
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ float bcast(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+// Entry i of the real residual and Jacobian at (tk, ak, on): lane i < 2m takes harmonic
+// l = i mod m + 1, its real part for i < m and imaginary part otherwise.  Columns t_1..t_K,
+// alpha_1..alpha_K; zero for inactive points and for lanes >= 2m.
+template <int K>
+__device__ __forceinline__ void w_residual(const float2* __restrict__ zp, const float2* __restrict__ h2, int i, int m,
+                                           int T, const float* tk, const float* ak, const bool* on, float& r,
+                                           float* jc) {
+    const float Tf = (float)T, invT = 1.0f / Tf, twoinvT = 2.0f / Tf;
+    r = 0.f;
+#pragma unroll
+    for (int c = 0; c < 2 * K; ++c) jc[c] = 0.f;
+    if (i >= 2 * m) return;
+    const bool re = i < m;
+    const int l = (re ? i : i - m) + 1;
+    const float2 h = h2[l - 1];
+    const float w = 6.283185307179586f * (float)l * invT;
+    float2 phi = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (!on[k]) continue;
+        const float2 g = cmul(h, phasor(l, tk[k], T, invT, twoinvT));
+        phi.x += ak[k] * g.x;
+        phi.y += ak[k] * g.y;
+        // dPhi/dt_k = a_k i w g, dPhi/dalpha_k = g
+        jc[k] = re ? -ak[k] * w * g.y : ak[k] * w * g.x;
+        jc[K + k] = re ? g.x : g.y;
+    }
+    const float2 zl = zp[l - 1];
+    r = re ? zl.x - phi.x : zl.y - phi.y;
+}
+
+// In place: b <- L^{-1} b for V vectors held one entry per lane.
+template <int M2, int V>
+__device__ __forceinline__ void w_forward(const float (&row)[M2], const float (&invd)[M2], float (&b)[V], int i) {
+#pragma unroll
+    for (int c = 0; c < M2; ++c) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const float y = bcast(b[v], c) * invd[c];
+            b[v] = i == c ? y : (i > c ? b[v] - row[c] * y : b[v]);
+        }
+    }
+}
+
+template <int K, int M2>
+__global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, const float* __restrict__ z,
+                                                    const int32_t* __restrict__ n, const float2* __restrict__ h2,
+                                                    float* __restrict__ t_io, float* __restrict__ a_io,
+                                                    const uint8_t* __restrict__ act, float* __restrict__ loss_out) {
+    constexpr int kWaves = 256 / 64;
+    __shared__ float2 s_psi[kWaves][2 * M2 + 1];
+    const int i = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int pix_raw = blockIdx.x * kWaves + wv;
+    const bool valid = pix_raw < A.P;
+    const int pix = valid ? pix_raw : A.P - 1;
+    const int m = A.m, T = A.T;
+    const float Tf = (float)T, invT = 1.0f / Tf, twoinvT = 2.0f / Tf;
+    float tk[K], ak[K];
+    bool on[K];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t q = (int64_t)pix * K + k;
+        tk[k] = t_io[q];
+        ak[k] = a_io[q];
+        on[k] = act[q] != 0;
+        any |= on[k];
+    }
+    // characteristic function Psi_j, j = 0..2m, at theta_1
+    for (int j = i; j <= 2 * m; j += 64) {
+        float2 v = make_float2(j == 0 ? 1.f : 0.f, 0.f);
+        if (j > 0) {
+            const float2 h = h2[j - 1];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (!on[k]) continue;
+                const float2 g = cmul(h, phasor(j, tk[k], T, invT, twoinvT));
+                v.x += ak[k] * g.x;
+                v.y += ak[k] * g.y;
+            }
+        }
+        s_psi[wv][j] = v;
+    }
+    __syncthreads();
+    // row i of Sigma
+    float row[M2];
+    {
+        const float2* ps = s_psi[wv];
+        const bool ri = i < m;
+        const int a = (ri ? i : i - m) + 1;
+        const float2 pa = i < 2 * m ? ps[a] : make_float2(0.f, 0.f);
+        const float mui = ri ? pa.x : pa.y;
+        float dg = 0.f;
+#pragma unroll
+        for (int c = 0; c < M2; ++c) {
+            float v;
+            if (i >= 2 * m || c >= 2 * m) {
+                v = c == i ? 1.f : 0.f;
+            } else {
+                const bool rc = c < m;
+                const int b = (rc ? c : c - m) + 1;
+                const float2 pb = ps[b];
+                const float2 s = ps[a + b];
+                const int d = a - b;
+                float2 df = ps[d >= 0 ? d : -d];
+                if (d < 0) df.y = -df.y;
+                if (ri && rc) v = 0.5f * (s.x + df.x);
+                else if (!ri && !rc) v = 0.5f * (df.x - s.x);
+                else if (ri) v = 0.5f * (s.y - df.y);           // E[cos_a sin_b]
+                else v = 0.5f * (s.y + df.y);                   // E[sin_a cos_b]
+                v -= mui * (rc ? pb.x : pb.y);
+            }
+            row[c] = v;
+            if (c == i) dg = v;
+        }
+        const float tr = wave_sum_f(i < 2 * m ? dg : 0.f);
+        const float ridge = 1e-5f * tr / (float)(2 * m);
+#pragma unroll
+        for (int c = 0; c < M2; ++c)
+            if (c == i && i < 2 * m) row[c] += ridge;
+    }
+    // Cholesky, row-oriented: after step j lane i >= j holds L_ij in row[j]
+    float invd[M2];
+#pragma unroll
+    for (int j = 0; j < M2; ++j) {
+        const float d = bcast(row[j], j);
+        const float piv = sqrtf(fmaxf(d, 1e-30f));
+        const float inv = 1.0f / piv;
+        invd[j] = inv;
+        const float lj = row[j] * inv;
+        row[j] = lj;
+#pragma unroll
+        for (int c = j + 1; c < M2; ++c) row[c] -= lj * bcast(lj, c);
+    }
+    const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m);
+    const float nq = (float)n[pix];
+    auto loss_at = [&](const float* tt, const float* aa) {
+        float b[1];
+        float jc[2 * K];
+        w_residual<K>(zp, h2, i, m, T, tt, aa, on, b[0], jc);
+        w_forward<M2, 1>(row, invd, b, i);
+        return nq * wave_sum_f(b[0] * b[0]);
+    };
+    float loss = loss_at(tk, ak);
+    float mu = 1e-3f;
+    if (any) {
+        for (int it = 0; it < witers; ++it) {
+            float b[1 + 2 * K];
+            float jc[2 * K];
+            w_residual<K>(zp, h2, i, m, T, tk, ak, on, b[0], jc);
+#pragma unroll
+            for (int c = 0; c < 2 * K; ++c) b[1 + c] = jc[c];
+            w_forward<M2, 1 + 2 * K>(row, invd, b, i);
+            // normal equations (identical in every lane)
+            float Am[2 * K][2 * K], g[2 * K];
+#pragma unroll
+            for (int p = 0; p < 2 * K; ++p) {
+                g[p] = wave_sum_f(b[1 + p] * b[0]);
+#pragma unroll
+                for (int q = 0; q <= p; ++q) {
+                    Am[p][q] = wave_sum_f(b[1 + p] * b[1 + q]);
+                    Am[q][p] = Am[p][q];
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < 2 * K; ++p) Am[p][p] += mu * (Am[p][p] + 1e-12f);
+            // Cholesky solve of the small system
+            float Lm[2 * K][2 * K], y[2 * K], dlt[2 * K];
+#pragma unroll
+            for (int p = 0; p < 2 * K; ++p) {
+#pragma unroll
+                for (int q = 0; q <= p; ++q) {
+                    float sacc = Am[p][q];
+#pragma unroll
+                    for (int r2 = 0; r2 < q; ++r2) sacc -= Lm[p][r2] * Lm[q][r2];
+                    Lm[p][q] = p == q ? sqrtf(fmaxf(sacc, 1e-38f)) : sacc / Lm[q][q];
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < 2 * K; ++p) {
+                float sacc = g[p];
+#pragma unroll
+                for (int q = 0; q < p; ++q) sacc -= Lm[p][q] * y[q];
+                y[p] = sacc / Lm[p][p];
+            }
+#pragma unroll
+            for (int p = 2 * K - 1; p >= 0; --p) {
+                float sacc = y[p];
+#pragma unroll
+                for (int q = p + 1; q < 2 * K; ++q) sacc -= Lm[q][p] * dlt[q];
+                dlt[p] = sacc / Lm[p][p];
+            }
+            float tn[K], an[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                tn[k] = on[k] ? wrap_t(tk[k] + dlt[k], Tf) : tk[k];
+                an[k] = on[k] ? ak[k] + dlt[K + k] : 0.f;
+            }
+            project_capped_simplex<K>(an, on);
+            const float ln = loss_at(tn, an);
+            if (ln < loss) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    tk[k] = tn[k];
+                    ak[k] = an[k];
+                }
+                loss = ln;
+                mu = fmaxf(mu * 0.1f, 1e-7f);
+            } else {
+                mu = fminf(mu * 10.f, 1e7f);
+            }
+        }
+    }
+    if (!valid || i != 0) return;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t q = (int64_t)pix * K + k;
+        t_io[q] = tk[k];
+        a_io[q] = ak[k];
+    }
+    loss_out[pix] = loss;
+}
+
 // ----------------------------------------------------------------------------- denoisers
 // Solve the leading D x D block of M x = b by M = L diag(d) L^T (unit lower L), with
 // reciprocals of the pivots.  The pivot d_j = M_jj - sum_k L_jk^2 d_k is the square of the
@@ -1444,6 +1720,25 @@ hipError_t launch_smle(const srt3d_params& p, const float* z, const int32_t* n, 
                                                st.hhat, st.scal, st.t[src], st.alpha[src], st.active[src], st.t[dst],
                                                st.alpha[dst], st.active[dst], loss));
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_wsmle(const srt3d_params& p, const double* irf, int irf_len, int irf_origin, const float* z,
+                        const int32_t* n, const srt3d_state& st, int half, int witers, float* loss, void* spec,
+                        hipStream_t s) {
+    const IterArgs A = make_args(p);
+    float2* h2 = reinterpret_cast<float2*>(spec);
+    hipLaunchKernelGGL(spectrum_kernel, dim3(1), dim3(1024), 0, s, irf, irf_len, irf_origin, p.T, 2 * p.m, h2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 grid((unsigned)((A.P + 3) / 4));
+#define SRT3D_WSMLE(M2_)                                                                                            \
+    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((wsmle_kernel<KK, M2_>), grid, dim3(256), 0, s, A, witers, z, n, h2,    \
+                                           st.t[half], st.alpha[half], st.active[half], loss))
+    if (2 * p.m <= 16) { SRT3D_WSMLE(16); }
+    else if (2 * p.m <= 32) { SRT3D_WSMLE(32); }
+    else { SRT3D_WSMLE(64); }
+#undef SRT3D_WSMLE
     return hipGetLastError();
 }
 

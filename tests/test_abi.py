@@ -148,6 +148,23 @@ def test_invalid_reconstruction_arguments(lib):
         assert lib.srt3d_smle(fake, fake, fake, 5, 2, ctypes.byref(p), starts, ctypes.byref(st), loss, fake, 1 << 20,
                               None) == -1
     assert lib.srt3d_smle(fake, fake, fake, 5, 2, ctypes.byref(p), 2, ctypes.byref(st), fake, fake, 16, None) == -2
+    # precision weighting: m > 32 or 2 m >= T, witers outside [0, 1000], small workspace
+    assert lib.srt3d_smle_weighted_workspace_bytes(ctypes.byref(p)) > 0
+    for change in (dict(m=33, T=1024), dict(m=4, T=8)):
+        q = L._Params()
+        ctypes.pointer(q)[0] = p
+        for k, v in change.items():
+            setattr(q, k, v)
+        assert lib.srt3d_smle_weighted_workspace_bytes(ctypes.byref(q)) == 0
+        assert lib.srt3d_smle_weighted(fake, fake, fake, 5, 2, ctypes.byref(q), 2, 10, ctypes.byref(st), fake, fake,
+                                       1 << 20, None) == -1
+        assert lib.srt3d_weighted_fit(ctypes.byref(st), fake, fake, fake, 5, 2, ctypes.byref(q), 10, fake, fake,
+                                      1 << 20, None) == -1
+    for witers in (-1, 1001):
+        assert lib.srt3d_weighted_fit(ctypes.byref(st), fake, fake, fake, 5, 2, ctypes.byref(p), witers, fake, fake,
+                                      1 << 20, None) == -1
+    assert lib.srt3d_weighted_fit(ctypes.byref(st), fake, fake, fake, 5, 2, ctypes.byref(p), 10, fake, fake, 16,
+                                  None) == -2
     st2 = L._State()
     ctypes.pointer(st2)[0] = st
     st2.cur = 2

@@ -1,0 +1,158 @@
+"""GPU parity of eq. (6) with the precision-matrix weighting (srt3d_weighted_fit,
+srt3d_smle_weighted) against the FP64 oracle, through the C ABI: the weighted loss at a shared
+first estimate (the covariance, its factor and the whitening), the Levenberg-Marquardt steps
+from it, noiseless recovery, and the two-step entry point against its parts."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2203_00952_amd as srt
+import synth
+from oracle import model as OM
+from oracle import smle as OSM
+from oracle import srt3d as O
+from oracle import weighted as OW
+from tests.gpu_common import circ_abs, device, to_complex
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(**kw):
+    print("case weighted", " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+CASES = [
+    ("mid", synth.FrameSpec(48, 40, 4096, 8.0, 200.0, 1.0, 1, seed=7), 16, 1, 4),
+    ("small_m", synth.FrameSpec(24, 24, 1024, 3.0, 300.0, 2.0, 1, seed=3), 4, 1, 3),
+    ("spurious", synth.FrameSpec(24, 24, 1024, 3.0, 300.0, 2.0, 1, seed=3), 4, 2, 3),
+    ("layered", synth.FrameSpec(36, 28, 8192, 8.0, 2000.0, 0.5, 3, seed=5), 16, 3, 3),
+    ("m32", synth.FrameSpec(20, 24, 4096, 6.0, 300.0, 1.0, 1, seed=9), 32, 1, 2),
+]
+
+
+def _setup(spec, m, K, starts, dev):
+    f = synth.make_frame(spec, device=dev)
+    z, n = srt.sketch(f.stamps, f.offsets, spec.T, m)
+    torch.cuda.synchronize()
+    params = srt.Params.default(spec.rows, spec.cols, spec.T, m, K)
+    op = O.Params(spec.T, m, K, iters=params.iters, R=params.R, Rb=params.Rb, r_min=params.r_min,
+                  tau_z=params.tau_z)
+    zc = to_complex(z)
+    nn = n.cpu().numpy().astype(np.int64)
+    st1 = OSM.smle(zc, nn, f.irf, f.irf_origin, op, starts)["state"]
+    # the state as the device holds it
+    st1 = O.State(st1.t.astype(np.float32).astype(np.float64), st1.alpha.astype(np.float32).astype(np.float64),
+                  st1.active.copy())
+    rec = srt.Reconstructor(params, dev)
+    irf = torch.from_numpy(f.irf).to(dev)
+    rec.smle(z, n, irf, f.irf_origin, 1)          # allocates and fills the constants; points replaced below
+    hhat = OM.irf_spectrum(f.irf, f.irf_origin, spec.T, m)
+    hhat2 = OM.irf_spectrum(f.irf, f.irf_origin, spec.T, 2 * m)
+    L = OW.whitener(OW.covariance(st1.t, st1.alpha, st1.active, hhat2, spec.T, m))
+    return f, z, n, zc, nn, rec, irf, st1, hhat, L
+
+
+def _download(rec):
+    t, a, act = (x.cpu().numpy() for x in rec.state())
+    return O.State(t.astype(np.float64), a.astype(np.float64), act.astype(bool))
+
+
+@pytest.mark.parametrize("name,spec,m,K,starts", CASES)
+def test_weighted_loss_at_a_shared_first_estimate(name, spec, m, K, starts):
+    """No steps: the returned loss is n ||L^{-1} r||^2 at theta_1 with Sigma(theta_1) built,
+    ridged and factored on the device."""
+    dev = device()
+    _case(test="loss0", frame=name, P=spec.P, m=m, K=K)
+    f, z, n, zc, nn, rec, irf, st1, hhat, L = _setup(spec, m, K, starts, dev)
+    rec.set_state(torch.from_numpy(st1.t), torch.from_numpy(st1.alpha), torch.from_numpy(st1.active))
+    loss = rec.weighted_fit(z, n, irf, f.irf_origin, 0).cpu().numpy()
+    ref = OW.weighted_loss(zc, nn, st1, hhat, L, spec.T)
+    err = np.abs(loss - ref) / np.maximum(ref, 1e-3)
+    print("weighted loss rel err: median", float(np.median(err)), "max", float(err.max()))
+    assert np.mean(err <= 1e-3) >= 0.99
+    assert err.max() <= 2e-2
+    g = _download(rec)
+    np.testing.assert_array_equal(g.t, st1.t)                 # no steps: points untouched
+    np.testing.assert_array_equal(g.alpha, st1.alpha)
+
+
+@pytest.mark.parametrize("name,spec,m,K,starts", CASES)
+def test_weighted_steps_match_oracle(name, spec, m, K, starts):
+    dev = device()
+    witers = 20
+    _case(test="steps", frame=name, P=spec.P, m=m, K=K, witers=witers)
+    f, z, n, zc, nn, rec, irf, st1, hhat, L = _setup(spec, m, K, starts, dev)
+    rec.set_state(torch.from_numpy(st1.t), torch.from_numpy(st1.alpha), torch.from_numpy(st1.active))
+    loss = rec.weighted_fit(z, n, irf, f.irf_origin, witers).cpu().numpy()
+    g = _download(rec)
+    r, lr = OW.weighted_fit(zc, nn, st1, hhat, L, spec.T, witers)
+    # Identifiable points (alpha >= 0.05 at theta_1) of pixels whose fit has settled in the
+    # oracle (its 20-step points are its 60-step points): there the device must land on the
+    # oracle's points.  A spurious extra point of tiny alpha (a K-point fit of a pixel with fewer
+    # surfaces) drifts over a nearly flat loss, where FP32 and FP64 steps may take different
+    # paths; such points are held to the loss checks below only (the "spurious" case has no
+    # identifiable second point at all).
+    r60, _ = OW.weighted_fit(zc, nn, st1, hhat, L, spec.T, 60)
+    settled = (np.where(r.active, circ_abs(r60.t - r.t, spec.T), 0).max(1) <= 1e-3) & \
+              (np.abs(r60.alpha - r.alpha).max(1) <= 1e-4)
+    ident = st1.active & (st1.alpha >= 0.05) & settled[:, None]
+    ok = (circ_abs(g.t - r.t, spec.T) <= 0.01) & (np.abs(g.alpha - r.alpha) <= 1e-3)
+    print("settled pixels:", settled.mean(), "identifiable points:", int(ident.sum()),
+          "of them with the oracle's values:", ok[ident].mean() if ident.any() else None)
+    if name != "spurious":
+        assert ident.sum() >= 0.3 * spec.P
+        assert ok[ident].mean() >= 0.99
+    # everywhere: the steps only lower the weighted loss; on settled pixels whose points are all
+    # identifiable, the device's points are as good as the oracle's under its weighting
+    assert np.all(loss <= OW.weighted_loss(zc, nn, st1, hhat, L, spec.T) * (1 + 2e-2) + 1e-3)
+    lg = OW.weighted_loss(zc, nn, g, hhat, L, spec.T)
+    whole = settled & np.all(~st1.active | (st1.alpha >= 0.05), 1)
+    assert np.all((lg <= lr * (1 + 1e-2) + 1e-3)[whole])
+
+
+def test_noiseless_two_surfaces_are_recovered():
+    dev = device()
+    T, m, rows, cols, K = 2048, 8, 16, 16, 2
+    P = rows * cols
+    rng = np.random.default_rng(6)
+    sig = 3.0
+    o = int(np.ceil(6 * sig))
+    irf = np.exp(-0.5 * (np.arange(-o, o + 1) / sig) ** 2)
+    hhat = OM.irf_spectrum(irf, o, T, m)
+    t = np.stack([rng.uniform(0, T / 2, P), rng.uniform(T / 2, T, P)], 1)
+    alpha = rng.uniform(0.15, 0.45, (P, K))
+    act = np.ones((P, K), bool)
+    zc = OM.model_sketch(t, alpha, act, hhat, T)
+    z = torch.from_numpy(np.stack([zc.real, zc.imag], -1).astype(np.float32)).to(dev)
+    n = torch.full((P,), 500, dtype=torch.int32, device=dev)
+    params = srt.Params.default(rows, cols, T, m, K)
+    rec = srt.Reconstructor(params, dev)
+    irf_d = torch.from_numpy(irf).to(dev)
+    _case(test="noiseless", P=P)
+    rec.smle(z, n, irf_d, o, 1)
+    start_t = t + rng.uniform(-0.5, 0.5, (P, K))
+    rec.set_state(torch.from_numpy(start_t), torch.from_numpy(alpha * 0.9), torch.from_numpy(act))
+    loss = rec.weighted_fit(z, n, irf_d, o, 60)
+    g = _download(rec)
+    print("max loss", float(loss.max()), "max dt", float(circ_abs(g.t - t, T).max()))
+    assert np.max(circ_abs(g.t - t, T)) < 5e-3
+    np.testing.assert_allclose(g.alpha, alpha, atol=2e-4)
+
+
+def test_two_step_entry_point_equals_its_parts():
+    dev = device()
+    spec, m, K, starts = CASES[0][1:]
+    f = synth.make_frame(spec, device=dev)
+    z, n = srt.sketch(f.stamps, f.offsets, spec.T, m)
+    params = srt.Params.default(spec.rows, spec.cols, spec.T, m, K)
+    irf = torch.from_numpy(f.irf).to(dev)
+    _case(test="two_step")
+    a = srt.Reconstructor(params, dev)
+    la = a.smle_weighted(z, n, irf, f.irf_origin, starts, 15)
+    b = srt.Reconstructor(params, dev)
+    b.smle(z, n, irf, f.irf_origin, starts)
+    lb = b.weighted_fit(z, n, irf, f.irf_origin, 15)
+    torch.cuda.synchronize()
+    assert torch.equal(la, lb)
+    for x, y in zip(a.state(), b.state()):
+        assert torch.equal(x, y)
