@@ -324,6 +324,27 @@ def main():
     ev_same = bool(torch.equal(n2, n)) and (args.sketch != "binned" or bool(torch.equal(z2, z)))
     ev_alg = 8.0 * N + 8.0 * m * P + 4.0 * P          # events in, sketch + counts out
     del z2, n2, ev_pix, ev_st, ev_ws
+
+    # the pixelwise comparison estimators on the same sketch (outside the timed steps): W = I from
+    # four starts, then 20 steps of the precision-weighted fit (eq. 6 with W = Sigma^-1)
+    pw = srt.Reconstructor(params, dev)
+    starts, wsteps = 4, 20
+    weighted = m <= 32 and 2 * m < T
+    pw.smle(z, n, irf, frame.irf_origin, starts)
+    if weighted:
+        pw.weighted_fit(z, n, irf, frame.irf_origin, wsteps)
+    e_p = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e_p[0].record(stream)
+    pw.smle(z, n, irf, frame.irf_origin, starts)
+    e_p[1].record(stream)
+    if weighted:
+        pw.weighted_fit(z, n, irf, frame.irf_origin, wsteps)
+    e_p[2].record(stream)
+    torch.cuda.synchronize()
+    pixelwise = {"smle_starts": starts, "smle_steps_per_start": w.iters, "smle_ms": e_p[0].elapsed_time(e_p[1]),
+                 "weighted_fit_steps": wsteps if weighted else 0,
+                 "weighted_fit_ms": e_p[1].elapsed_time(e_p[2]) if weighted else None}
+    del pw
     res = {
         "metric": METRIC,
         "value": args.steps / wall,
@@ -347,6 +368,7 @@ def main():
         "event_stream_sketch": {"ms": ev_ms, "events_per_s": N / (ev_ms * 1e-3),
                                 "hbm_frac": ev_alg / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                 "algorithmic_bytes": ev_alg, "same_as_step_sketch": ev_same},
+        "pixelwise_estimators": pixelwise,
         "sketch_ms": {"mean": float(sk_ms.mean()), "p50": float(np.percentile(sk_ms, 50)),
                       "p99": float(np.percentile(sk_ms, 99))},
         "srt3d_ms": {"mean": float(rc_ms.mean()), "p50": float(np.percentile(rc_ms, 50)),
