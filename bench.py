@@ -80,7 +80,7 @@ def cpu_baseline(frame, z_gpu, n_gpu, w, params):
     zc = zc[..., 0] + 1j * zc[..., 1]
     nn = n_gpu.cpu().numpy().astype(np.int64)
     rng = np.random.default_rng(0)
-    S = 2048
+    S = min(2048, spec.P)
     sel = np.sort(rng.choice(spec.P, S, replace=False))
     it_sample = 5
     op = O.Params(spec.T, w.m, w.K_max, iters=params.iters, r_min=params.r_min)

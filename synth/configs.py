@@ -44,6 +44,11 @@ PRESETS = {
         "billion", FrameSpec(512, 512, 8192, 8.0, 4000.0, 0.5, 3, seed=5), m=32, K_max=3,
         iters=50, description="512x512 px, T=8192, <=3 surfaces/px, ~4000 photons/px, SBR=0.5, m=32",
         r_min=100.0),
+    "camouflage": Workload(
+        "camouflage", FrameSpec(32, 32, 153, 2.0, 200.0, 2.0, 2, seed=11), m=10, K_max=2,
+        iters=50, description="32x32 px, T=153, two surfaces on most pixels (netting in front), "
+                              "~200 photons/px, SBR=2, m=10 (the shape of the camouflage frame of Section 4)",
+        r_min=5.0),
 }
 
 

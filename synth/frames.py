@@ -35,7 +35,7 @@ class FrameSpec:
     sigma: float          # IRF standard deviation in bins
     lam: float            # mean photons per pixel (signal + background)
     sbr: float            # frame-average signal-to-background ratio
-    layers: int = 1       # 1: nearest surface per pixel; 3: layered scene
+    layers: int = 1       # 1: nearest surface per pixel; 2: netting in front; 3: layered scene
     seed: int = 0
 
     @property
@@ -96,7 +96,9 @@ def _rect(rng, rows, cols):
 
 
 def make_scene(spec: FrameSpec) -> Scene:
-    """Piecewise-planar scene: back wall plus three rectangles (plus a mesh if layered)."""
+    """Piecewise-planar scene: back wall plus three rectangles (plus a mesh if layered: a
+    checkerboard mesh over object and wall for 3 layers, a netting with holes in front of the
+    nearest surface for 2)."""
     rng = np.random.default_rng(spec.seed)
     R, C, T = spec.rows, spec.cols, spec.T
     lo, hi = 6.0 * spec.sigma, T - 6.0 * spec.sigma
@@ -137,8 +139,22 @@ def make_scene(spec: FrameSpec) -> Scene:
         depth = np.stack([np.where(has_net, net, 0.0), np.where(has_obj, obj_depth, 0.0), wall], -1)
         weight = np.stack([f_net, f_obj, f_wall], -1)
         refl = np.stack([np.full((R, C), r_net), obj_refl, np.full((R, C), r_wall)], -1)
+    elif spec.layers == 2:
+        # camouflage-like: a netting plane in front of most pixels, the object or the wall behind
+        net = _plane(rng, R, C, rng.uniform(0.22 * T, 0.3 * T), 0.05, (R - 1) / 2, (C - 1) / 2)
+        r_net = rng.uniform(0.5, 1.5)
+        cell = max(2, R // 8)
+        ii, jj = np.meshgrid(np.arange(R), np.arange(C), indexing="ij")
+        has_net = ((ii % cell) != 0) | ((jj % cell) != 0)      # a grid of holes, one per cell
+        front = has_obj & (obj_depth < wall)
+        back = np.where(front, obj_depth, wall)
+        r_back = np.where(front, obj_refl, r_wall)
+        f_net = np.where(has_net, 0.4, 0.0)
+        depth = np.stack([np.where(has_net, net, 0.0), back], -1)
+        weight = np.stack([f_net, 1.0 - f_net], -1)
+        refl = np.stack([np.full((R, C), r_net), r_back], -1)
     else:
-        raise ValueError("layers must be 1 or 3")
+        raise ValueError("layers must be 1, 2 or 3")
 
     depth = np.where(weight > 0, np.clip(depth, lo, hi), 0.0)
     L = depth.shape[-1]

@@ -240,6 +240,21 @@ def test_end_to_end_layered():
     assert ok.mean() >= 0.995
 
 
+def test_end_to_end_camouflage():
+    """Two surfaces on most pixels (netting in front of the object or wall), T = 153, m = 10,
+    K_max = 2: the shape of the camouflage frame of Section 4."""
+    dev = device()
+    w = synth.preset("camouflage")
+    fr = Frame(w.frame, w.m, w.K_max, dev, r_min=w.r_min)
+    _case(test="e2e_camouflage", P=w.frame.P)
+    out = fr.rec.reconstruct(fr.z, fr.n, fr.irf, fr.f.irf_origin)
+    torch.cuda.synchronize()
+    r = O.reconstruct(fr.zc, fr.nn, fr.f.irf, fr.f.irf_origin, fr.spec.rows, fr.spec.cols, fr.op)
+    ok = pixel_pass(out["depth"].cpu().numpy(), out["active"].cpu().numpy(), r["depth"], r["active"], fr.spec.T)
+    print("camouflage end to end: pixels within 1 bin", ok.mean(), "failing", int((~ok).sum()))
+    assert ok.mean() >= 0.995
+
+
 def test_deterministic_and_resumable():
     dev = device()
     fr = tiny(dev)

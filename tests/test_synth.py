@@ -44,6 +44,18 @@ def test_layered_scene():
     assert np.min(sc.depth[both, 2] - sc.depth[both, 0]) > 8192 / 32
 
 
+def test_camouflage_scene():
+    """Two surfaces on most pixels: a netting in front, the nearest object or the wall behind."""
+    w = synth.preset("camouflage")
+    sc = synth.make_scene(w.frame)
+    k = (sc.weight > 0).sum(1)
+    assert set(np.unique(k)) == {1, 2} and np.mean(k == 2) > 0.9
+    np.testing.assert_allclose(sc.weight.sum(1), 1.0)
+    both = k == 2
+    assert np.all(sc.depth[both, 1] > sc.depth[both, 0])
+    assert w.frame.T == 153 and w.m == 10 and w.K_max == 2
+
+
 def test_irf_and_histogram():
     h, o = binned_gaussian_irf(8.0)
     assert o == 48 and h.size == 97
