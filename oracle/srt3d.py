@@ -14,6 +14,9 @@ leaves open, chosen once and used identically by the HIP path:
   intensity   gated weighted mean of photon counts n*alpha, threshold r_min
   background  alpha_0 = 1 - sum alpha (eq. 1), b = n alpha_0 / T, box filter
   output      per-pixel points sorted by depth, inactive slots last
+  merge/birth optional, every `birth_every` iterations (RT3D's split and merge of points, not
+              described in the paper): points closer than T/(2m) merge; a free slot takes the
+              residual's matched-filter peak when it carries at least r_min photons
 
 Depths are in bins on the circle [0, T) (the sketch is periodic in t).
 
@@ -45,6 +48,7 @@ class Params:
     lambda_z: float = 1.0  # relaxation of the depth denoiser
     tau_z: float = 0.0     # depth gate in bins; 0 = 3 * sigma of the impulse response
     r_min: float = 1.0     # photons below which a point is removed
+    birth_every: int = 0   # iterations between merge/birth stages; 0 = none
 
     @property
     def stride(self) -> int:
@@ -320,12 +324,73 @@ def default_tau_z(irf, origin: int, p: Params) -> float:
     return p.tau_z if p.tau_z > 0 else 3.0 * irf_sigma(irf, origin)
 
 
+# ---------------------------------------------------------------------------
+# merge and birth of points
+# ---------------------------------------------------------------------------
+def merge_points(st: State, p: Params) -> State:
+    """Two active points of a pixel closer than T/(2m) (circular) become one, in slot order: the
+    lower slot k takes t = the alpha-weighted circular mean, alpha = the sum; the other slot is
+    cleared."""
+    T, K = p.T, st.t.shape[1]
+    t, a, act = st.t.copy(), st.alpha.copy(), st.active.copy()
+    for k in range(K):
+        for q in range(k + 1, K):
+            d = circ_diff(t[:, q] - t[:, k], T)                          # signed, (-T/2, T/2]
+            both = act[:, k] & act[:, q] & (np.abs(d) * 2 * p.m < T)
+            s = a[:, k] + a[:, q]
+            w = np.where(s > 0, a[:, q] / np.where(s > 0, s, 1.0), 0.5)
+            t[:, k] = np.where(both, wrap(t[:, k] + w * d, T), t[:, k])
+            a[:, k] = np.where(both, s, a[:, k])
+            a[:, q] = np.where(both, 0.0, a[:, q])
+            act[:, q] &= ~both
+    return State(t, a, act)
+
+
+def birth_points(st: State, z, n, hhat, p: Params) -> State:
+    """Where a pixel has a free slot and photons: the sketched matched filter of the init
+    (grid 0, s, 2s, ...) on the residual z - Phi(theta), restricted to grid points at circular
+    distance >= T/m from every active point; the maximum (lowest tau on ties) with amplitude
+    a = max(0, c / sum |hhat|^2) becomes a point in the first free slot iff n a >= r_min; then
+    alpha is projected onto {alpha >= 0, sum alpha <= 1}."""
+    T, m, K = p.T, p.m, st.t.shape[1]
+    z = np.asarray(z, dtype=np.complex128)
+    n = np.asarray(n, dtype=np.int64)
+    P = z.shape[0]
+    s = p.stride
+    G = -(-T // s)
+    tau = np.arange(G, dtype=np.int64) * s
+    ell = np.arange(1, m + 1, dtype=np.int64)
+    Eg = np.exp(-1j * 2.0 * np.pi * np.mod(tau[:, None] * ell[None, :], T) / T)    # [G, m]
+    e2 = float(np.sum(np.abs(hhat) ** 2))
+    w = z - np.einsum("pk,pkl->pl", np.where(st.active, st.alpha, 0.0), atoms(st.t, hhat, T))
+    c = ((np.conj(hhat) * w) @ Eg.T).real                                       # [P, G]
+    dist = np.abs(circ_diff(tau[None, None, :] - st.t[:, :, None], T))          # [P, K, G]
+    excluded = np.any(st.active[:, :, None] & (dist * m < T), axis=1)
+    c = np.where(excluded, -np.inf, c)
+    g = np.argmax(c, axis=1)
+    rows = np.arange(P)
+    best = c[rows, g]
+    a = np.where(np.isfinite(best), np.maximum(0.0, best / e2), 0.0)
+    free = ~st.active
+    slot = np.argmax(free, axis=1)
+    born = free.any(1) & (n > 0) & np.isfinite(best) & (n * a >= p.r_min)
+    t, al, act = st.t.copy(), st.alpha.copy(), st.active.copy()
+    t[rows[born], slot[born]] = tau[g[born]]
+    al[rows[born], slot[born]] = a[born]
+    act[rows[born], slot[born]] = True
+    return State(t, project_capped_simplex(np.where(act, al, 0.0), act), act)
+
+
 def iterate(st: State, z, n, hhat, rows, cols, p: Params, tau_z: float, iters: int) -> State:
+    """`iters` x (data step, depth denoiser, intensity denoiser); with birth_every = B > 0, after
+    iteration i (counted from 1 in this call) with i % B == 0 and i < iters, merge then birth."""
     gam_t, gam_a = step_sizes(n, hhat, p)
-    for _ in range(iters):
+    for it in range(iters):
         st = data_step(st, z, n, hhat, p, gam_t, gam_a)
         st = depth_denoise(st, rows, cols, p, tau_z)
         st = intensity_denoise(st, n, rows, cols, p, tau_z)
+        if p.birth_every > 0 and (it + 1) % p.birth_every == 0 and it + 1 < iters:
+            st = birth_points(merge_points(st, p), z, n, hhat, p)
     return st
 
 
@@ -445,5 +510,5 @@ __all__ = [
     "Params", "State", "wrap", "circ_diff", "project_capped_simplex", "step_sizes", "init_points",
     "data_step", "depth_denoise", "intensity_denoise", "background", "output", "iterate",
     "reconstruct", "chol_solve", "window_weight", "depth_denoise_loop", "intensity_denoise_loop",
-    "default_tau_z", "irf_spectrum", "atoms", "unit_phasors",
+    "default_tau_z", "irf_spectrum", "atoms", "unit_phasors", "merge_points", "birth_points",
 ]

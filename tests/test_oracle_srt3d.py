@@ -290,3 +290,83 @@ def test_reconstruction_shift_equivariance():
     np.testing.assert_array_equal(a["active"], b["active"])
     np.testing.assert_allclose(O.circ_diff(b["depth"] - a["depth"] - D, T)[a["active"]], 0, atol=1e-6)
     np.testing.assert_allclose(b["intensity"], a["intensity"], atol=1e-6)
+
+
+# ------------------------------------------------------------------ merge and birth
+def test_birth_adds_the_missing_orthogonal_surface():
+    """Delta response, m even, surfaces T/2 apart: with only the first active, the residual is
+    exactly the second atom, whose grid position and amplitude the birth returns exactly."""
+    T, m = 480, 6
+    p = O.Params(T, m, 2)
+    hhat = OM.irf_spectrum([1.0], 0, T, m)
+    t = np.array([[60.0, 300.0]])
+    alpha = np.array([[0.25, 0.45]])
+    z = _noiseless(t, alpha, np.ones((1, 2), bool), hhat, T)
+    st = O.State(np.array([[60.0, 0.0]]), np.array([[0.25, 0.0]]), np.array([[True, False]]))
+    b = O.birth_points(st, z, np.array([50]), hhat, p)
+    np.testing.assert_array_equal(b.active, [[True, True]])
+    np.testing.assert_allclose(b.t, t, atol=1e-12)
+    np.testing.assert_allclose(b.alpha, alpha, atol=1e-12)
+    # too few photons for the new point (n a = 0.45 n < r_min), or no free slot: unchanged
+    b2 = O.birth_points(st, z, np.array([2]), hhat, O.Params(T, m, 2, r_min=1.0))
+    np.testing.assert_array_equal(b2.active, st.active)
+    full = O.State(np.array([[60.0, 120.0]]), np.array([[0.25, 0.1]]), np.array([[True, True]]))
+    b3 = O.birth_points(full, z, np.array([50]), hhat, p)
+    np.testing.assert_array_equal(b3.t, full.t)
+
+
+def test_birth_respects_the_exclusion_distance():
+    """A residual peaked at an active point (its amplitude underestimated) cannot spawn a point
+    closer than T/m to it."""
+    T, m = 1024, 8
+    p = O.Params(T, m, 3, r_min=0.0)
+    h, o = _gauss_irf(3.0)
+    hhat = OM.irf_spectrum(h, o, T, m)
+    rng = np.random.default_rng(7)
+    P = 40
+    t = rng.uniform(0, T, (P, 1))
+    z = _noiseless(t, np.full((P, 1), 0.8), np.ones((P, 1), bool), hhat, T)
+    st = O.State(np.concatenate([t, np.zeros((P, 2))], 1), np.concatenate([np.full((P, 1), 0.3), np.zeros((P, 2))], 1),
+                 np.array([[True, False, False]] * P))
+    b = O.birth_points(st, z, np.full(P, 100), hhat, p)
+    born = b.active[:, 1]
+    d = np.abs(O.circ_diff(b.t[:, 1] - t[:, 0], T))
+    assert np.all(d[born] * m >= T)
+    assert not b.active[:, 2].any()          # one birth per stage
+
+
+def test_merge_weighted_circular_mean():
+    T, m = 1000, 10                          # merge below T/(2m) = 50 bins
+    p = O.Params(T, m, 3)
+    st = O.State(np.array([[100.0, 130.0, 700.0], [990.0, 20.0, 500.0], [100.0, 160.0, 300.0]]),
+                 np.array([[0.2, 0.3, 0.1], [0.1, 0.3, 0.2], [0.2, 0.3, 0.1]]),
+                 np.array([[True, True, True], [True, True, True], [True, True, False]]))
+    r = O.merge_points(st, p)
+    np.testing.assert_allclose(r.t[0, :1], [100.0 + 0.6 * 30.0])
+    np.testing.assert_allclose(r.alpha[0], [0.5, 0.0, 0.1])
+    np.testing.assert_array_equal(r.active[0], [True, False, True])
+    np.testing.assert_allclose(r.t[1, 0], 990.0 + 0.75 * 30.0 - 1000.0)     # across the wrap
+    np.testing.assert_allclose(r.alpha[1], [0.4, 0.0, 0.2])
+    np.testing.assert_array_equal(r.active[2], [True, True, False])         # 60 bins apart: kept
+    np.testing.assert_array_equal(r.t[2], st.t[2])
+
+
+def test_iterations_with_births_find_a_surface_the_start_lacks():
+    """Noiseless two-surface pixels started from one surface only: with merge/birth stages
+    every 5 iterations the second surface is found; without them it is not."""
+    T, m, rows, cols = 1024, 8, 6, 6
+    P = rows * cols
+    h, o = _gauss_irf(2.0)
+    hhat = OM.irf_spectrum(h, o, T, m)
+    t = np.stack([np.full(P, 200.0), np.full(P, 600.0)], 1)
+    alpha = np.stack([np.full(P, 0.3), np.full(P, 0.4)], 1)
+    z = _noiseless(t, alpha, np.ones((P, 2), bool), hhat, T)
+    n = np.full(P, 500)
+    st0 = O.State(np.stack([t[:, 0], np.zeros(P)], 1), np.stack([alpha[:, 0], np.zeros(P)], 1),
+                  np.stack([np.ones(P, bool), np.zeros(P, bool)], 1))
+    tau_z = 6.0
+    with_b = O.iterate(st0, z, n, hhat, rows, cols, O.Params(T, m, 2, birth_every=5), tau_z, 40)
+    without = O.iterate(st0, z, n, hhat, rows, cols, O.Params(T, m, 2), tau_z, 40)
+    assert with_b.active.all() and not without.active[:, 1].any()
+    d = np.abs(O.circ_diff(np.sort(with_b.t, 1) - t, T))
+    assert np.max(d) < 0.5
