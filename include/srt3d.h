@@ -51,7 +51,8 @@ enum srt3d_precision {
 enum srt3d_stage {
     SRT3D_STAGE_DATA = 0,      /* gradient step on depth then intensity, projection */
     SRT3D_STAGE_DEPTH = 1,     /* point-cloud (depth) denoiser */
-    SRT3D_STAGE_INTENSITY = 2  /* intensity denoiser and point removal */
+    SRT3D_STAGE_INTENSITY = 2, /* intensity denoiser and point removal */
+    SRT3D_STAGE_BIRTH = 3      /* merge of close points, birth of a point from the residual */
 };
 
 /* Limits of the reconstruction kernels. */
@@ -82,6 +83,8 @@ typedef struct srt3d_params {
     float lambda_z;       /* depth-denoiser relaxation (default 1) */
     float tau_z;          /* depth gate in bins; <= 0 = 3 x std of the impulse response */
     float r_min;          /* photons below which a point is removed (default 1) */
+    int32_t birth_every;  /* iterations between merge/birth stages in srt3d_iterate; 0 = none
+                             (default) */
 } srt3d_params;
 
 /*
@@ -218,7 +221,16 @@ int srt3d_sketch_from_hist(const uint16_t* d_hist, int32_t P, int32_t T, int32_t
  *              st->cur is set to 0
  *   d_ws       workspace of srt3d_init_workspace_bytes(p) bytes
  * srt3d_step:    runs one stage (srt3d_stage) on the current state.
- * srt3d_iterate: runs `iters` full iterations (data, depth, intensity).
+ * srt3d_iterate: runs `iters` full iterations (data, depth, intensity); with
+ *   p->birth_every = B > 0, after iteration i (counted from 1 in this call) with i % B == 0 and
+ *   i < iters, the merge/birth stage runs before the next data step.
+ * Merge/birth stage (RT3D's split and merge of points, cited by Section 3 for scenes with
+ *   several surfaces, not described in the paper; in place): active points of a pixel closer
+ *   than T/(2m) merge into the lower slot (alpha-weighted circular mean depth, summed alpha);
+ *   then a pixel with a free slot and n > 0 takes the peak of the initialisation's matched
+ *   filter on its residual z - Phi(theta), over grid points at circular distance >= T/m from
+ *   every active point (amplitude max(0, c / sum |hhat|^2)), into its first free slot when
+ *   n * amplitude >= r_min; alpha is then projected.
  * srt3d_finalize: background b = n max(0, 1 - sum alpha) / T (box filtered) and the output
  *   points per pixel sorted by depth with inactive slots last:
  *   d_depth, d_intensity float32 [P][K_max] (bins; photons n alpha), d_active uint8 [P][K_max],
@@ -226,7 +238,7 @@ int srt3d_sketch_from_hist(const uint16_t* d_hist, int32_t P, int32_t T, int32_t
  * srt3d_reconstruct: init + iterate(p->iters) + finalize.
  * Constraints: rows, cols >= 1, 1 <= m <= SRT3D_MAX_M_RECON, m <= T/2, T * 8 <= 65536,
  * 1 <= K_max <= SRT3D_MAX_K, 0 <= R <= SRT3D_MAX_R, 0 <= Rb <= 8, irf_len >= 1,
- * 0 <= irf_origin < irf_len, iters >= 0, eta_t, eta_a >= 0.
+ * 0 <= irf_origin < irf_len, iters >= 0, eta_t, eta_a >= 0, birth_every >= 0.
  * ------------------------------------------------------------------------------------- */
 size_t srt3d_init_workspace_bytes(const srt3d_params* p);
 int srt3d_init(const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len,

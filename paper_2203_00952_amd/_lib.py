@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsrt3d.so")
 
 SRT3D_OK, SRT3D_EINVAL, SRT3D_ENOMEM, SRT3D_EDEVICE = 0, -1, -2, -3
 PRECISIONS = {"fp32": 0, "fp16x2": 1, "bf16x3": 2}
-STAGES = {"data": 0, "depth": 1, "intensity": 2}
+STAGES = {"data": 0, "depth": 1, "intensity": 2, "birth": 3}
 MAX_M_RECON, MAX_K, MAX_R, NSCAL, MAX_STARTS = 64, 3, 3, 8, 64
 
 
@@ -32,7 +32,7 @@ class _Params(ctypes.Structure):
                 ("m", ctypes.c_int32), ("K_max", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("R", ctypes.c_int32), ("Rb", ctypes.c_int32), ("init_stride", ctypes.c_int32),
                 ("eta_t", ctypes.c_float), ("eta_a", ctypes.c_float), ("lambda_z", ctypes.c_float),
-                ("tau_z", ctypes.c_float), ("r_min", ctypes.c_float)]
+                ("tau_z", ctypes.c_float), ("r_min", ctypes.c_float), ("birth_every", ctypes.c_int32)]
 
 
 class _State(ctypes.Structure):
@@ -271,6 +271,7 @@ class Params:
     lambda_z: float = 1.0
     tau_z: float = 0.0
     r_min: float = 1.0
+    birth_every: int = 0
 
     @classmethod
     def default(cls, rows, cols, T, m, K_max=1, **kw) -> "Params":

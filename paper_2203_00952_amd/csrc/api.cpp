@@ -26,6 +26,7 @@ int check_params(const srt3d_params* p) {
     if (!(p->eta_t >= 0.f) || !(p->eta_a >= 0.f) || !(p->lambda_z >= 0.f) || !(p->r_min >= 0.f))
         return SRT3D_EINVAL;
     if (p->tau_z != p->tau_z) return SRT3D_EINVAL;   // NaN
+    if (p->birth_every < 0) return SRT3D_EINVAL;
     return SRT3D_OK;
 }
 
@@ -59,6 +60,7 @@ void srt3d_params_default(srt3d_params* p, int32_t rows, int32_t cols, int32_t T
     p->lambda_z = 1.f;
     p->tau_z = 0.f;
     p->r_min = 1.f;
+    p->birth_every = 0;
 }
 
 int srt3d_sketch(const int32_t* d_stamps, int64_t N, const int64_t* d_offsets, int32_t P, int32_t T, int32_t m,
@@ -220,7 +222,7 @@ int srt3d_step(srt3d_state* st, const float* d_z, const int32_t* d_n, const srt3
     int rc = check_params(p);
     if (rc != SRT3D_OK) return rc;
     if ((rc = check_state(st)) != SRT3D_OK) return rc;
-    if (!d_n || (stage == SRT3D_STAGE_DATA && !d_z)) return SRT3D_EINVAL;
+    if (!d_n || ((stage == SRT3D_STAGE_DATA || stage == SRT3D_STAGE_BIRTH) && !d_z)) return SRT3D_EINVAL;
     hipStream_t s = as_stream(stream);
     const int c = st->cur;
     hipError_t e;
@@ -228,10 +230,11 @@ int srt3d_step(srt3d_state* st, const float* d_z, const int32_t* d_n, const srt3
         case SRT3D_STAGE_DATA: e = launch_data_step(*p, d_z, d_n, *st, c, s); break;
         case SRT3D_STAGE_DEPTH: e = launch_depth_denoise(*p, *st, c, 1 - c, s); break;
         case SRT3D_STAGE_INTENSITY: e = launch_intensity_denoise(*p, d_n, *st, c, 1 - c, s); break;
+        case SRT3D_STAGE_BIRTH: e = launch_birth(*p, d_z, d_n, *st, c, s); break;
         default: return SRT3D_EINVAL;
     }
     if (e != hipSuccess) return SRT3D_EDEVICE;
-    if (stage != SRT3D_STAGE_DATA) st->cur = 1 - c;
+    if (stage == SRT3D_STAGE_DEPTH || stage == SRT3D_STAGE_INTENSITY) st->cur = 1 - c;
     return SRT3D_OK;
 }
 
@@ -244,13 +247,20 @@ int srt3d_iterate(srt3d_state* st, const float* d_z, const int32_t* d_n, const s
     if (iters == 0) return SRT3D_OK;
     // data step, then per iteration the depth and intensity denoisers of iteration it and the data
     // step of iteration it + 1 (none after the last): one fused launch, or with several points per
-    // pixel a depth-denoiser launch and the fused rest
+    // pixel a depth-denoiser launch and the fused rest.  With merge/birth stages, an iteration
+    // followed by one ends without the data step, which then follows the stage.
     hipStream_t s = as_stream(stream);
     if (launch_data_step(*p, d_z, d_n, *st, st->cur, s) != hipSuccess) return SRT3D_EDEVICE;
     for (int it = 0; it < iters; ++it) {
+        const bool birth = p->birth_every > 0 && (it + 1) % p->birth_every == 0 && it + 1 < iters;
         int next = st->cur;
-        if (launch_iteration(*p, d_z, d_n, *st, st->cur, it + 1 < iters, s, &next) != hipSuccess) return SRT3D_EDEVICE;
+        if (launch_iteration(*p, d_z, d_n, *st, st->cur, it + 1 < iters && !birth, s, &next) != hipSuccess)
+            return SRT3D_EDEVICE;
         st->cur = next;
+        if (birth) {
+            if (launch_birth(*p, d_z, d_n, *st, st->cur, s) != hipSuccess) return SRT3D_EDEVICE;
+            if (launch_data_step(*p, d_z, d_n, *st, st->cur, s) != hipSuccess) return SRT3D_EDEVICE;
+        }
     }
     return SRT3D_OK;
 }

@@ -69,6 +69,8 @@ hipError_t launch_smle(const srt3d_params& p, const float* z, const int32_t* n, 
 hipError_t launch_wsmle(const srt3d_params& p, const double* irf, int irf_len, int irf_origin, const float* z,
                         const int32_t* n, const srt3d_state& st, int half, int witers, float* loss, void* spec,
                         hipStream_t s);
+hipError_t launch_birth(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st, int cur,
+                        hipStream_t s);
 hipError_t launch_depth_denoise(const srt3d_params& p, const srt3d_state& st, int src, int dst, hipStream_t s);
 hipError_t launch_intensity_denoise(const srt3d_params& p, const int32_t* n, const srt3d_state& st, int src,
                                     int dst, hipStream_t s);

@@ -773,6 +773,118 @@ __global__ __launch_bounds__(256) void smle_kernel(IterArgs A, int starts, int i
     }
 }
 
+// ----------------------------------------------------------------------------- merge and birth
+// Optional stage between iterations (RT3D's split and merge of points; the paper cites RT3D for
+// scenes with several surfaces per pixel but does not describe the moves): active points of a
+// pixel closer than T/(2m) merge, in slot order, into the lower slot (alpha-weighted circular
+// mean depth, summed alpha); then a pixel with a free slot and photons runs the sketched matched
+// filter of the initialisation on its residual z - Phi(theta), over the grid 0, s, 2s, ... at
+// circular distance >= T/m from every active point, and the peak (lowest tau on ties), with
+// amplitude max(0, c / sum |hhat|^2), fills the first free slot when it carries >= r_min
+// photons; alpha is then projected.  One thread per pixel, the residual kept in LDS.
+constexpr int kBirthThreads = 64;
+
+template <int K>
+__global__ __launch_bounds__(kBirthThreads) void birth_kernel(IterArgs A, int stride, int G,
+                                                              const float* __restrict__ z,
+                                                              const int32_t* __restrict__ n,
+                                                              const float* __restrict__ hhat,
+                                                              const float* __restrict__ scal, float* __restrict__ t_io,
+                                                              float* __restrict__ a_io, uint8_t* __restrict__ act_io) {
+    __shared__ float2 s_w[kBirthThreads][SRT3D_MAX_M_RECON];
+    __shared__ float2 s_h[SRT3D_MAX_M_RECON];
+    for (int l = threadIdx.x; l < A.m; l += kBirthThreads) s_h[l] = reinterpret_cast<const float2*>(hhat)[l];
+    __syncthreads();
+    const int pix = blockIdx.x * kBirthThreads + threadIdx.x;
+    if (pix >= A.P) return;
+    const int T = A.T, m = A.m;
+    const float Tf = (float)T, invT = 1.0f / Tf, twoinvT = 2.0f / Tf;
+    float tk[K], ak[K];
+    bool on[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t q = (int64_t)pix * K + k;
+        tk[k] = t_io[q];
+        ak[k] = a_io[q];
+        on[k] = act_io[q] != 0;
+    }
+    // merge
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int q = k + 1; q < K; ++q) {
+            if (!(on[k] && on[q])) continue;
+            const float d = circ_diff(tk[q] - tk[k], Tf, invT);
+            if (!(fabsf(d) * (float)(2 * m) < Tf)) continue;
+            const float sum = ak[k] + ak[q];
+            const float w = sum > 0.f ? ak[q] / sum : 0.5f;
+            tk[k] = wrap_t(tk[k] + w * d, Tf);
+            ak[k] = sum;
+            ak[q] = 0.f;
+            on[q] = false;
+        }
+    int slot = -1;
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k)
+        if (!on[k]) slot = k;
+    const int np = n[pix];
+    if (slot >= 0 && np > 0) {
+        const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m);
+        float2* w = s_w[threadIdx.x];
+        for (int l = 0; l < m; ++l) {
+            const float2 h = s_h[l];
+            float2 e = zp[l];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (!on[k]) continue;
+                const float2 g = cmul(h, phasor(l + 1, tk[k], T, invT, twoinvT));
+                e.x -= ak[k] * g.x;
+                e.y -= ak[k] * g.y;
+            }
+            w[l] = e;
+        }
+        float best = 0.f;
+        int bg = -1;
+        for (int g = 0; g < G; ++g) {
+            const int tau = g * stride;
+            bool excluded = false;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (on[k] && fabsf(circ_diff((float)tau - tk[k], Tf, invT)) * (float)m < Tf) excluded = true;
+            if (excluded) continue;
+            // c = Re sum_l conj(hhat_l e^{i w_l tau}) w_l, the phase (l tau) mod T kept exactly
+            float c = 0.f;
+            int kph = 0;
+            for (int l = 0; l < m; ++l) {
+                kph += tau;
+                if (kph >= T) kph -= T;
+                const float2 q = cmul(s_h[l], phasor_int(kph, twoinvT));
+                const float2 wl = w[l];
+                c += q.x * wl.x + q.y * wl.y;
+            }
+            if (bg < 0 || c > best) {
+                best = c;
+                bg = g;
+            }
+        }
+        const float e2 = scal[4];
+        const float a = (bg >= 0 && e2 > 0.f) ? fmaxf(0.f, best / e2) : 0.f;
+        if (bg >= 0 && (float)np * a >= A.r_min) {
+            tk[slot] = (float)(bg * stride);
+            ak[slot] = a;
+            on[slot] = true;
+        }
+    }
+    project_capped_simplex<K>(ak, on);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t q = (int64_t)pix * K + k;
+        t_io[q] = tk[k];
+        a_io[q] = ak[k];
+        act_io[q] = on[k] ? 1 : 0;
+    }
+}
+
 // ----------------------------------------------------------------------------- precision weighting
 // Eq. (6) with W = Sigma^{-1}, pixel by pixel, as the second step after the pixelwise W = I
 // estimate theta_1.  Sigma is the covariance of the sketch's 2m real coordinates
@@ -1720,6 +1832,16 @@ hipError_t launch_smle(const srt3d_params& p, const float* z, const int32_t* n, 
                                                st.hhat, st.scal, st.t[src], st.alpha[src], st.active[src], st.t[dst],
                                                st.alpha[dst], st.active[dst], loss));
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_birth(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st, int cur,
+                        hipStream_t s) {
+    const IterArgs A = make_args(p);
+    const InitGrid g = init_grid(p);
+    const dim3 grid((unsigned)((A.P + kBirthThreads - 1) / kBirthThreads));
+    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((birth_kernel<KK>), grid, dim3(kBirthThreads), 0, s, A, g.stride, g.G, z, n,
+                                           st.hhat, st.scal, st.t[cur], st.alpha[cur], st.active[cur]));
     return hipGetLastError();
 }
 

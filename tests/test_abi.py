@@ -133,7 +133,7 @@ def test_invalid_reconstruction_arguments(lib):
     st.hhat = st.scal = 0x1000
     args = (fake, fake, fake, 5, 2, ctypes.byref(p), ctypes.byref(st), fake, 1 << 20, None)
     bad = [dict(K_max=4), dict(m=65), dict(R=4), dict(rows=0), dict(iters=-1), dict(eta_t=-1.0),
-           dict(init_stride=1024), dict(T=16384)]
+           dict(init_stride=1024), dict(T=16384), dict(birth_every=-1)]
     for change in bad:
         q = L._Params()
         ctypes.pointer(q)[0] = p
@@ -169,7 +169,8 @@ def test_invalid_reconstruction_arguments(lib):
     ctypes.pointer(st2)[0] = st
     st2.cur = 2
     assert lib.srt3d_step(ctypes.byref(st2), fake, fake, ctypes.byref(p), 0, None) == -1
-    assert lib.srt3d_step(ctypes.byref(st), fake, fake, ctypes.byref(p), 3, None) == -1
+    assert lib.srt3d_step(ctypes.byref(st), fake, fake, ctypes.byref(p), 4, None) == -1
+    assert lib.srt3d_step(ctypes.byref(st), None, fake, ctypes.byref(p), 3, None) == -1    # birth needs z
     st2.cur = 0
     st2.scal = None
     assert lib.srt3d_iterate(ctypes.byref(st2), fake, fake, ctypes.byref(p), 1, None) == -1

@@ -255,6 +255,70 @@ def test_end_to_end_camouflage():
     assert ok.mean() >= 0.995
 
 
+def _camouflage(dev, **pk):
+    w = synth.preset("camouflage")
+    return Frame(w.frame, w.m, w.K_max, dev, r_min=w.r_min, **pk)
+
+
+def test_merge_birth_stage_from_shared_state():
+    """The merge/birth stage on a shared state where half the pixels lost their second point
+    and a quarter carry two points a few bins apart."""
+    dev = device()
+    fr = _camouflage(dev)
+    fr.gpu_init()
+    st = O.iterate(O.init_points(fr.zc, fr.nn, fr.hhat, fr.op), fr.zc, fr.nn, fr.hhat, fr.spec.rows,
+                   fr.spec.cols, fr.op, fr.tau_z, 5)
+    P = fr.spec.P
+    rng = np.random.default_rng(1)
+    drop = rng.uniform(size=P) < 0.5
+    st.active[drop, 1] = False
+    st.alpha[drop, 1] = 0.0
+    close = ~drop & (rng.uniform(size=P) < 0.5) & st.active.all(1)
+    st.t[close, 1] = np.mod(st.t[close, 0] + rng.uniform(-3, 3, close.sum()), fr.spec.T)
+    st = O.State(st.t.astype(np.float32).astype(np.float64), st.alpha.astype(np.float32).astype(np.float64),
+                 st.active)
+    _case(test="birth_stage", P=P, dropped=int(drop.sum()), close=int(close.sum()))
+    fr.upload(st)
+    fr.rec.step("birth", fr.z, fr.n)
+    g = fr.download()
+    r = O.birth_points(O.merge_points(st, fr.op), fr.zc, fr.nn, fr.hhat, fr.op)
+    same = (g.active == r.active).all(1)
+    dt = np.where(r.active, circ_abs(g.t - r.t, fr.spec.T), 0).max(1)
+    da = np.abs(g.alpha - r.alpha).max(1)
+    ok = same & (dt <= 1e-3) & (da <= 1e-4)
+    born = r.active.sum(1) > st.active.sum(1)
+    merged = O.merge_points(st, fr.op).active.sum(1) < st.active.sum(1)     # freed slots may refill
+    print("births", int(born.sum()), "merges", int(merged.sum()), "pixels equal:", ok.mean())
+    assert born.sum() > 0.3 * drop.sum() and merged.sum() > 0
+    # the birth's grid argmax is decided in FP32 here and FP64 in the oracle: a peak between two
+    # grid points (stride 1 at T = 153) can flip to the neighbour on a near-tie
+    assert ok.mean() >= 0.99
+
+
+def test_iterations_with_births_match_oracle():
+    """Started from one surface per pixel, iterations with merge/birth stages every 10
+    iterations recover the netting and the surface behind it as the oracle does."""
+    dev = device()
+    fr = _camouflage(dev, birth_every=10)
+    op = O.with_params(fr.op, birth_every=10)
+    fr.gpu_init()
+    st0 = O.init_points(fr.zc, fr.nn, fr.hhat, op)
+    st0.active[:, 1] = False
+    st0.alpha[:, 1] = 0.0
+    fr.upload(st0)
+    _case(test="iterations_births", P=fr.spec.P)
+    fr.rec.iterate(fr.z, fr.n, 40)
+    out = fr.rec.finalize(fr.n)
+    torch.cuda.synchronize()
+    r = O.iterate(st0, fr.zc, fr.nn, fr.hhat, fr.spec.rows, fr.spec.cols, op, fr.tau_z, 40)
+    d, _, a = O.output(r, fr.nn)
+    ok = pixel_pass(out["depth"].cpu().numpy(), out["active"].cpu().numpy(), d, a, fr.spec.T)
+    two = a.sum(1) == 2
+    print("pixels within 1 bin", ok.mean(), "two points (oracle)", two.mean())
+    assert two.mean() > 0.8
+    assert ok.mean() >= 0.995
+
+
 def test_deterministic_and_resumable():
     dev = device()
     fr = tiny(dev)
