@@ -66,6 +66,26 @@ def sketch_traffic(method: str, workload: str):
     return float(m_b.group(1))
 
 
+VALU_PEAK = 256 * 2.4e9        # wave64 VALU instructions per second: one per clock per CU
+
+
+def sketch_valu(method: str, workload: str):
+    """VALU wave instructions per binned-sketch launch from the committed counter summary of the
+    throughput workload, if it describes the current kernel source (else None)."""
+    if method != "binned" or workload != "throughput":
+        return None
+    path = os.path.join(ROOT, "profiles", "valu_counters_throughput.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2203_00952_amd", "csrc", "binned.hip"), "rb").read()).hexdigest()
+    m_sha = re.search(r"binned\.hip sha256:\s*([0-9a-f]{64})", text)
+    m_v = re.search(r"sketch_binned_kernel VALU wave instructions per launch:\s*([0-9.eE+]+)", text)
+    if not m_sha or not m_v or m_sha.group(1) != sha:
+        return None
+    return float(m_v.group(1))
+
+
 def cpu_baseline(frame, z_gpu, n_gpu, w, params):
     """Time the FP64 oracle on this host, single-threaded, on a bounded sample of the step."""
     import numpy as np
@@ -288,6 +308,7 @@ def main():
     alg_bytes = 4.0 * N + 8.0 * (P + 1) + 8.0 * m * P + 4.0 * P
     achieved = alg_bytes / (sk_ms.mean() * 1e-3) / 1e9
     traffic = sketch_traffic(args.sketch, w.name)
+    valu = sketch_valu(args.sketch, w.name)
     kernel = SKETCH_KERNELS[args.sketch][0]
 
     # the other sketch path on the same frame, for reference (outside the timed steps)
@@ -377,6 +398,12 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes},
+        # the same kernel against its binding limit, VALU issue (counts from the committed
+        # rocprofv3 summary, the time live)
+        "valu_roofline": None if valu is None else {
+            "kernel": kernel, "valu_wave_insts_per_launch": valu,
+            "achieved": valu / (sk_ms.mean() * 1e-3), "peak": VALU_PEAK, "unit": "wave instructions/s",
+            "frac": valu / (sk_ms.mean() * 1e-3) / VALU_PEAK},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(frame, z, n, w, params)
