@@ -982,6 +982,35 @@ __device__ __forceinline__ void w_forward(const float (&row)[M2], const float (&
     }
 }
 
+// In place: b <- Linv b with lane i holding row i of Linv (lower triangular): a broadcast and an
+// FMA per column.
+template <int M2, int V>
+__device__ __forceinline__ void w_apply_inverse(const float (&linv)[M2], float (&b)[V]) {
+    float y[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) y[v] = 0.f;
+#pragma unroll
+    for (int c = 0; c < M2; ++c)
+#pragma unroll
+        for (int v = 0; v < V; ++v) y[v] += linv[c] * bcast(b[v], c);
+#pragma unroll
+    for (int v = 0; v < V; ++v) b[v] = y[v];
+}
+
+// Whitening b <- L^{-1} b: with rows of up to 32 entries through the explicit inverse (formed
+// once per pixel), wider rows by forward substitution (the inverse would not fit in registers).
+template <int M2>
+struct Whitener {
+    static constexpr bool kInverse = M2 <= 32;
+    float row[M2], invd[M2];
+    float linv[kInverse ? M2 : 1];
+    template <int V>
+    __device__ __forceinline__ void apply(float (&b)[V], int i) const {
+        if constexpr (kInverse) w_apply_inverse<M2, V>(linv, b);
+        else w_forward<M2, V>(row, invd, b, i);
+    }
+};
+
 template <int K, int M2>
 __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, const float* __restrict__ z,
                                                     const int32_t* __restrict__ n, const float2* __restrict__ h2,
@@ -1023,7 +1052,9 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
     }
     __syncthreads();
     // row i of Sigma
-    float row[M2];
+    Whitener<M2> wh;
+    float (&row)[M2] = wh.row;
+    float (&invd)[M2] = wh.invd;
     {
         const float2* ps = s_psi[wv];
         const bool ri = i < m;
@@ -1060,7 +1091,6 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
             if (c == i && i < 2 * m) row[c] += ridge;
     }
     // Cholesky, row-oriented: after step j lane i >= j holds L_ij in row[j]
-    float invd[M2];
 #pragma unroll
     for (int j = 0; j < M2; ++j) {
         const float d = bcast(row[j], j);
@@ -1072,13 +1102,19 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
 #pragma unroll
         for (int c = j + 1; c < M2; ++c) row[c] -= lj * bcast(lj, c);
     }
+    if constexpr (Whitener<M2>::kInverse) {
+        // lane i: row i of L^{-1}, the forward substitution of the unit vectors
+#pragma unroll
+        for (int v = 0; v < M2; ++v) wh.linv[v] = i == v ? 1.f : 0.f;
+        w_forward<M2, M2>(row, invd, wh.linv, i);
+    }
     const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m);
     const float nq = (float)n[pix];
     auto loss_at = [&](const float* tt, const float* aa) {
         float b[1];
         float jc[2 * K];
         w_residual<K>(zp, h2, i, m, T, tt, aa, on, b[0], jc);
-        w_forward<M2, 1>(row, invd, b, i);
+        wh.apply(b, i);
         return nq * wave_sum_f(b[0] * b[0]);
     };
     float loss = loss_at(tk, ak);
@@ -1090,7 +1126,7 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
             w_residual<K>(zp, h2, i, m, T, tk, ak, on, b[0], jc);
 #pragma unroll
             for (int c = 0; c < 2 * K; ++c) b[1 + c] = jc[c];
-            w_forward<M2, 1 + 2 * K>(row, invd, b, i);
+            wh.apply(b, i);
             // normal equations (identical in every lane)
             float Am[2 * K][2 * K], g[2 * K];
 #pragma unroll
