@@ -311,6 +311,20 @@ def main():
     valu = sketch_valu(args.sketch, w.name)
     kernel = SKETCH_KERNELS[args.sketch][0]
 
+    # achievable HBM bandwidth on this device: a plain 1 GiB device-to-device copy (reads and
+    # writes 1 GiB each), outside the timed steps
+    src_b = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst_b = torch.empty_like(src_b)
+    dst_b.copy_(src_b)
+    e_c = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e_c[0].record(stream)
+    for _ in range(5):
+        dst_b.copy_(src_b)
+    e_c[1].record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * src_b.numel() * 4 * 5 / (e_c[0].elapsed_time(e_c[1]) * 1e-3) / 1e9
+    del src_b, dst_b
+
     # the other sketch path on the same frame, for reference (outside the timed steps)
     other = "photon" if args.sketch == "binned" else "binned"
     z2 = torch.empty_like(z)
@@ -397,7 +411,8 @@ def main():
         "latency_ms": {"p50": float(np.percentile(st_ms, 50)), "p99": float(np.percentile(st_ms, 99))},
         "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes},
+                     "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         # the same kernel against its binding limit, VALU issue (counts from the committed
         # rocprofv3 summary, the time live)
         "valu_roofline": None if valu is None else {
