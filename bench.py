@@ -231,6 +231,48 @@ def serving_report(args):
     print(json.dumps(res), flush=True)
 
 
+def table1_report(args):
+    """SRT3D reconstruction time per frame on synthetic frames of the shapes the paper's Table 1
+    times (141^2 .. 705^2 px, T = 4613, m = 5 and 10, one surface), 50 iterations (the paper does
+    not state its count; photons/px does not change the reconstruction's work).  Context only:
+    the paper's numbers come from another GPU, an unstated precision and the head dataset."""
+    import numpy as np
+    import torch
+
+    import paper_2203_00952_amd as srt
+    import synth
+
+    dev = torch.device("cuda:0")
+    paper_ms = {5: [6, 12, 28, 55, 68], 10: [7, 18, 35, 60, 88]}
+    out = {"workload": "table1", "T": 4613, "iters": 50, "photons_per_pixel": 100, "rows": []}
+    for si, side in enumerate((141, 282, 423, 564, 705)):
+        spec = synth.FrameSpec(side, side, 4613, 8.0, 100.0, 1.0, 1, seed=30 + si)
+        f = synth.make_frame(spec, device=dev)
+        irf = torch.from_numpy(f.irf).to(dev)
+        for m in (5, 10):
+            z, n = srt.sketch(f.stamps, f.offsets, spec.T, m)
+            params = srt.Params.default(side, side, spec.T, m, 1, iters=50)
+            rec = srt.Reconstructor(params, dev)
+            outb = None
+            for _ in range(2):
+                outb = rec.reconstruct(z, n, irf, f.irf_origin, out=outb)
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            reps = 10
+            ev[0].record()
+            for _ in range(reps):
+                rec.reconstruct(z, n, irf, f.irf_origin, out=outb)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / reps
+            out["rows"].append({"pixels": side * side, "side": side, "m": m, "srt3d_ms": ms,
+                                "frames_per_s": 1e3 / ms, "paper_ms_rtx3070_laptop": paper_ms[m][si]})
+            del rec, z, n
+        del f
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.workload == "precision":
@@ -238,6 +280,9 @@ def main():
         return
     if args.workload == "serving":
         serving_report(args)
+        return
+    if args.workload == "table1":
+        table1_report(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
