@@ -273,6 +273,50 @@ def table1_report(args):
     print(json.dumps(out), flush=True)
 
 
+def nsweep_report(args):
+    """Sketch and SRT3D times against photons per pixel on 256x256 frames (T = 4096, m = 16,
+    50 iterations): the sketch grows with the photon count, the reconstruction from the sketch
+    does not (the claim of Section 1 / Fig. 1 for SRT3D)."""
+    import torch
+
+    import paper_2203_00952_amd as srt
+    import synth
+
+    dev = torch.device("cuda:0")
+    out = {"workload": "nsweep", "pixels": 65536, "T": 4096, "m": 16, "iters": 50, "rows": []}
+    for lam in (10.0, 100.0, 1000.0, 4000.0):
+        spec = synth.FrameSpec(256, 256, 4096, 8.0, lam, 1.0, 1, seed=40)
+        f = synth.make_frame(spec, device=dev)
+        irf = torch.from_numpy(f.irf).to(dev)
+        params = srt.Params.default(256, 256, 4096, 16, 1, iters=50)
+        rec = srt.Reconstructor(params, dev)
+        z, n = srt.sketch(f.stamps, f.offsets, spec.T, 16, method="binned")
+        o = rec.reconstruct(z, n, irf, f.irf_origin)
+        torch.cuda.synchronize()
+        z2, n2 = srt.sketch(f.stamps, f.offsets, spec.T, 16, method="photon")
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        reps = 10
+        ev[0].record()
+        for _ in range(reps):
+            srt.sketch(f.stamps, f.offsets, spec.T, 16, z=z, n=n, method="binned")
+        ev[1].record()
+        for _ in range(reps):
+            srt.sketch(f.stamps, f.offsets, spec.T, 16, z=z2, n=n2, method="photon")
+        ev[2].record()
+        for _ in range(reps):
+            rec.reconstruct(z, n, irf, f.irf_origin, out=o)
+        ev[3].record()
+        torch.cuda.synchronize()
+        out["rows"].append({"photons_per_pixel": lam, "photons": int(f.stamps.numel()),
+                            "sketch_binned_ms": ev[0].elapsed_time(ev[1]) / reps,
+                            "sketch_photon_ms": ev[1].elapsed_time(ev[2]) / reps,
+                            "srt3d_ms": ev[2].elapsed_time(ev[3]) / reps})
+        del z2, n2
+        del f, z, n, rec
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.workload == "precision":
@@ -283,6 +327,9 @@ def main():
         return
     if args.workload == "table1":
         table1_report(args)
+        return
+    if args.workload == "nsweep":
+        nsweep_report(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
