@@ -319,6 +319,10 @@ def nsweep_report(args):
 
 def main():
     args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the library has no "
+                                   "multi-GPU path (pixels would shard with no communication)"}))
+        sys.exit(2)
     if args.workload == "precision":
         precision_report(args)
         return
@@ -331,10 +335,6 @@ def main():
     if args.workload == "nsweep":
         nsweep_report(args)
         return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
-                                   "part of this build (pixels shard with no communication)"}))
-        sys.exit(2)
 
     import numpy as np
     import torch
