@@ -19,4 +19,5 @@ from ._lib import (  # noqa: F401
     sketch,
     sketch_events,
     sketch_from_hist,
+    sketch_route,
 )

@@ -141,7 +141,19 @@ def cached_phase_table(T: int, device) -> torch.Tensor:
     return _TABLES[key]
 
 
-SKETCH_METHODS = ("photon", "binned")
+SKETCH_METHODS = ("photon", "binned", "auto")
+
+# The binned pass costs a per-pixel contraction over all T bins (a floor of ~62 us for 256x256
+# pixels at T = 4096, m = 16 on MI355X) plus little per photon; the photon pass costs m phase
+# lookups per photon.  Measured on that frame, the photon pass is faster below ~170 photons per
+# pixel (11 vs 61 us at 10, 43 vs 62 at 100, 194 vs 79 at 1000); both floors scale with the
+# harmonics and the binned one with T, so "auto" switches at N = 0.04 P T.
+AUTO_BINNED_PHOTONS_PER_PIXEL_BIN = 0.04
+
+
+def sketch_route(N: int, P: int, T: int, m: int) -> str:
+    """The route "auto" takes: binned for m <= 32 and at least 0.04 T photons per pixel."""
+    return "binned" if m <= 32 and N >= AUTO_BINNED_PHOTONS_PER_PIXEL_BIN * P * T else "photon"
 
 
 def sketch(stamps: torch.Tensor, offsets: torch.Tensor, T: int, m: int, *, acc=None, nacc=None, err=None,
@@ -149,10 +161,13 @@ def sketch(stamps: torch.Tensor, offsets: torch.Tensor, T: int, m: int, *, acc=N
     """Photon sketch (eq. 3).  Returns (z float32 [P, m, 2], n int32 [P]).
 
     method "photon": photon-parallel pass over the phase table (srt3d_sketch);
-    method "binned": per-pixel histogram on the FP16 matrix cores (srt3d_sketch_binned, m <= 32)."""
+    method "binned": per-pixel histogram on the FP16 matrix cores (srt3d_sketch_binned, m <= 32);
+    method "auto": the faster of the two for the frame's photons per pixel (sketch_route)."""
     if method not in SKETCH_METHODS:
         raise ValueError(f"sketch: unknown method {method!r}")
     P = offsets.numel() - 1
+    if method == "auto":
+        method = sketch_route(stamps.numel(), P, T, m)
     dev = offsets.device
     ps = _dev(stamps, torch.int32, "stamps")
     po = _dev(offsets, torch.int64, "offsets")

@@ -100,7 +100,8 @@ def percentile(values, q):
 # ----------------------------------------------------------------------------- GPU executor
 class Request:
     """One frame to serve: device stamps and offsets, the impulse response and its parameters.
-    `sketch` picks the sketch route ("binned" unless m > 32, where only "photon" applies)."""
+    `sketch` picks the sketch route (default "auto": binned for m <= 32 and at least 0.04 T
+    photons per pixel, else the photon pass)."""
 
     def __init__(self, rid, stamps, offsets, irf, irf_origin, params, arrival=0.0, sketch=None):
         self.rid = rid
@@ -108,7 +109,7 @@ class Request:
         self.irf, self.irf_origin = irf, irf_origin
         self.params = params
         self.arrival = arrival
-        self.sketch = sketch or ("binned" if params.m <= 32 else "photon")
+        self.sketch = sketch or "auto"
 
     def working_bytes(self) -> int:
         """Device memory the request holds while it runs: its photon stamps and offsets, the

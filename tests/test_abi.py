@@ -182,3 +182,12 @@ def test_binding_refuses_cpu_tensors():
     import torch
     with pytest.raises(TypeError):
         srt.sketch(torch.zeros(4, dtype=torch.int32), torch.zeros(3, dtype=torch.int64), 64, 4)
+
+
+def test_auto_sketch_route():
+    """"auto" takes the binned pass from 0.04 T photons per pixel (m <= 32), else the photon pass."""
+    assert srt.sketch_route(65536 * 1000, 65536, 4096, 16) == "binned"
+    assert srt.sketch_route(65536 * 100, 65536, 4096, 16) == "photon"
+    assert srt.sketch_route(1639, 10, 4096, 16) == "binned"          # 0.04 T P = 1638.4
+    assert srt.sketch_route(1638, 10, 4096, 16) == "photon"
+    assert srt.sketch_route(10 ** 9, 10, 4096, 33) == "photon"

@@ -169,3 +169,20 @@ def test_full_frame_sampled_pixels(preset):
     d = np.abs(zb - zpp) / (2e-5 * np.maximum(np.abs(zpp), floor))
     print("binned vs photon, max |dz| / (2 tol) =", float(d.max()))
     assert d.max() <= 1.0
+
+
+def test_auto_route_takes_the_faster_pass_bit_for_bit():
+    """method "auto": the photon pass's bits below 0.04 T photons per pixel, the binned pass's
+    bits above."""
+    dev = device()
+    rng = np.random.default_rng(17)
+    T, m, P = 4096, 16, 700
+    for lam, expect in ((20, "photon"), (400, "binned")):
+        counts = rng.poisson(lam, P)
+        stamps, offsets, _, _ = csr([rng.integers(0, T, c) for c in counts], dev)
+        _print_case(test="auto_route", lam=lam)
+        assert srt.sketch_route(stamps.numel(), P, T, m) == expect
+        za, na = srt.sketch(stamps, offsets, T, m, method="auto")
+        ze, ne = srt.sketch(stamps, offsets, T, m, method=expect)
+        torch.cuda.synchronize()
+        assert torch.equal(za, ze) and torch.equal(na, ne)
