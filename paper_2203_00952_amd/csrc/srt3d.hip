@@ -1917,9 +1917,15 @@ hipError_t launch_intensity_denoise(const srt3d_params& p, const int32_t* n, con
     return hipGetLastError();
 }
 
-// Whether an iteration runs as a depth-denoiser launch plus the fused rest (several points per
-// pixel: the fits dominate, and the fused kernel's ring would repeat them) or as one launch.
-static bool split_iteration(const srt3d_params& p) { return p.K_max >= 2; }
+// Whether an iteration runs as a depth-denoiser launch plus the fused rest or as one launch.
+// With several points per pixel the fits dominate and the fused kernel's ring repeats them
+// (1.9x at 8x16 tiles, R = 2), which costs more than the second launch on large frames; on
+// smaller ones the launches are latency bound and one launch wins.  Measured per 50 iterations
+// (fused / split): K = 3, m = 32: 128^2 0.96 / 1.46 ms, 256^2 1.38 / 1.78, 384^2 2.86 / 2.52,
+// 512^2 4.44 / 3.67; K = 2, m = 10: 32^2 0.53 / 0.70, 256^2 0.82 / 0.93, 512^2 2.43 / 2.07.
+static bool split_iteration(const srt3d_params& p) {
+    return p.K_max >= 2 && (int64_t)p.rows * p.cols >= (1 << 17);
+}
 
 hipError_t launch_iteration(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st, int src,
                             bool ds_next, hipStream_t s, int* out) {
