@@ -287,7 +287,7 @@ int srt3d_smle(const float* d_z, const int32_t* d_n, const double* d_irf, int32_
  * `witers` Levenberg-Marquardt steps on n ||L^{-1} [Re(z - Phi), Im(z - Phi)]||^2 over the
  * active points (a step kept iff it lowers that loss; mu from 1e-3, / 10 on success down to
  * 1e-7, * 10 on failure up to 1e7; alpha projected, t wrapped).  Points are neither added nor
- * removed.  One wave per pixel.
+ * removed.  One segment of 16, 32 or 64 lanes (>= 2m) per pixel.
  *   arguments as srt3d_smle, plus witers (0 <= witers <= SRT3D_MAX_WITERS); the workspace is
  *   srt3d_smle_weighted_workspace_bytes(p) bytes, 16-byte aligned
  *   d_loss     float32 [P]: the weighted loss at the returned points

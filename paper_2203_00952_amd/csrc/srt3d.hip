@@ -895,9 +895,9 @@ __global__ __launch_bounds__(kBirthThreads) void birth_kernel(IterArgs A, int st
 // lowers n ||L^{-1} r||^2 (mu from 1e-3, / 10 on success down to 1e-7, * 10 on failure up to
 // 1e7), alpha projected onto the constraint set, t wrapped.
 //
-// One wave per pixel; lane i owns row i of Sigma, then of L (row-oriented Cholesky with the
-// pivot column broadcast by readlane), and entry i of every whitened vector (forward
-// substitution one column at a time).  M2 >= 2m is the row length; rows 2m..M2-1 are identity.
+// One segment of M2 >= 2m lanes per pixel (a wave holds 64 / M2 pixels); lane i of a segment
+// owns row i of Sigma, then of L (row-oriented Cholesky with the pivot column broadcast across
+// the segment), and entry i of every whitened vector.  Rows 2m..M2-1 are identity.
 
 // hhat_l for l = 1..J (J <= 2 SRT3D_MAX_M_RECON), one harmonic per wave, the FP64 sums of the
 // frame setup.
@@ -929,13 +929,23 @@ __global__ __launch_bounds__(1024) void spectrum_kernel(const double* __restrict
     }
 }
 
-__device__ __forceinline__ float wave_sum_f(float v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+// A wave holds 64 / M2 pixels, one per segment of M2 lanes (M2 = 64: one pixel).  Broadcast of
+// lane `base + j` of the caller's segment: readlane when the segment is the wave, else a
+// cross-lane permute through the LDS crossbar (one instruction for every segment).
+template <int M2>
+__device__ __forceinline__ float sbcast(float v, int base, int j) {
+    if constexpr (M2 == 64)
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), j));
+    else
+        return __shfl(v, base + j, 64);
 }
 
-__device__ __forceinline__ float bcast(float v, int lane) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+// Sum over the caller's segment of M2 lanes (identical in all of them).
+template <int M2>
+__device__ __forceinline__ float seg_sum(float v) {
+#pragma unroll
+    for (int o = M2 / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
 // Entry i of the real residual and Jacobian at (tk, ak, on): lane i < 2m takes harmonic
@@ -969,14 +979,15 @@ __device__ __forceinline__ void w_residual(const float2* __restrict__ zp, const 
     r = re ? zl.x - phi.x : zl.y - phi.y;
 }
 
-// In place: b <- L^{-1} b for V vectors held one entry per lane.
+// In place: b <- L^{-1} b for V vectors held one entry per lane (row i of the segment at base).
 template <int M2, int V>
-__device__ __forceinline__ void w_forward(const float (&row)[M2], const float (&invd)[M2], float (&b)[V], int i) {
+__device__ __forceinline__ void w_forward(const float (&row)[M2], const float (&invd)[M2], float (&b)[V], int i,
+                                          int base) {
 #pragma unroll
     for (int c = 0; c < M2; ++c) {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            const float y = bcast(b[v], c) * invd[c];
+            const float y = sbcast<M2>(b[v], base, c) * invd[c];
             b[v] = i == c ? y : (i > c ? b[v] - row[c] * y : b[v]);
         }
     }
@@ -985,14 +996,14 @@ __device__ __forceinline__ void w_forward(const float (&row)[M2], const float (&
 // In place: b <- Linv b with lane i holding row i of Linv (lower triangular): a broadcast and an
 // FMA per column.
 template <int M2, int V>
-__device__ __forceinline__ void w_apply_inverse(const float (&linv)[M2], float (&b)[V]) {
+__device__ __forceinline__ void w_apply_inverse(const float (&linv)[M2], float (&b)[V], int base) {
     float y[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) y[v] = 0.f;
 #pragma unroll
     for (int c = 0; c < M2; ++c)
 #pragma unroll
-        for (int v = 0; v < V; ++v) y[v] += linv[c] * bcast(b[v], c);
+        for (int v = 0; v < V; ++v) y[v] += linv[c] * sbcast<M2>(b[v], base, c);
 #pragma unroll
     for (int v = 0; v < V; ++v) b[v] = y[v];
 }
@@ -1005,9 +1016,9 @@ struct Whitener {
     float row[M2], invd[M2];
     float linv[kInverse ? M2 : 1];
     template <int V>
-    __device__ __forceinline__ void apply(float (&b)[V], int i) const {
-        if constexpr (kInverse) w_apply_inverse<M2, V>(linv, b);
-        else w_forward<M2, V>(row, invd, b, i);
+    __device__ __forceinline__ void apply(float (&b)[V], int i, int base) const {
+        if constexpr (kInverse) w_apply_inverse<M2, V>(linv, b, base);
+        else w_forward<M2, V>(row, invd, b, i, base);
     }
 };
 
@@ -1017,26 +1028,26 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
                                                     float* __restrict__ t_io, float* __restrict__ a_io,
                                                     const uint8_t* __restrict__ act, float* __restrict__ loss_out) {
     constexpr int kWaves = 256 / 64;
-    __shared__ float2 s_psi[kWaves][2 * M2 + 1];
-    const int i = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int pix_raw = blockIdx.x * kWaves + wv;
+    constexpr int kPPW = 64 / M2;                      // pixels per wave, one per segment
+    __shared__ float2 s_psi[kWaves][kPPW][2 * M2 + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int seg = lane / M2, i = lane % M2, base = seg * M2;
+    const int pix_raw = (blockIdx.x * kWaves + wv) * kPPW + seg;
     const bool valid = pix_raw < A.P;
     const int pix = valid ? pix_raw : A.P - 1;
     const int m = A.m, T = A.T;
     const float Tf = (float)T, invT = 1.0f / Tf, twoinvT = 2.0f / Tf;
     float tk[K], ak[K];
     bool on[K];
-    bool any = false;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int64_t q = (int64_t)pix * K + k;
         tk[k] = t_io[q];
         ak[k] = a_io[q];
         on[k] = act[q] != 0;
-        any |= on[k];
     }
     // characteristic function Psi_j, j = 0..2m, at theta_1
-    for (int j = i; j <= 2 * m; j += 64) {
+    for (int j = i; j <= 2 * m; j += M2) {
         float2 v = make_float2(j == 0 ? 1.f : 0.f, 0.f);
         if (j > 0) {
             const float2 h = h2[j - 1];
@@ -1048,7 +1059,7 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
                 v.y += ak[k] * g.y;
             }
         }
-        s_psi[wv][j] = v;
+        s_psi[wv][seg][j] = v;
     }
     __syncthreads();
     // row i of Sigma
@@ -1056,7 +1067,7 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
     float (&row)[M2] = wh.row;
     float (&invd)[M2] = wh.invd;
     {
-        const float2* ps = s_psi[wv];
+        const float2* ps = s_psi[wv][seg];
         const bool ri = i < m;
         const int a = (ri ? i : i - m) + 1;
         const float2 pa = i < 2 * m ? ps[a] : make_float2(0.f, 0.f);
@@ -1084,7 +1095,7 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
             row[c] = v;
             if (c == i) dg = v;
         }
-        const float tr = wave_sum_f(i < 2 * m ? dg : 0.f);
+        const float tr = seg_sum<M2>(i < 2 * m ? dg : 0.f);
         const float ridge = 1e-5f * tr / (float)(2 * m);
 #pragma unroll
         for (int c = 0; c < M2; ++c)
@@ -1093,20 +1104,20 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
     // Cholesky, row-oriented: after step j lane i >= j holds L_ij in row[j]
 #pragma unroll
     for (int j = 0; j < M2; ++j) {
-        const float d = bcast(row[j], j);
+        const float d = sbcast<M2>(row[j], base, j);
         const float piv = sqrtf(fmaxf(d, 1e-30f));
         const float inv = 1.0f / piv;
         invd[j] = inv;
         const float lj = row[j] * inv;
         row[j] = lj;
 #pragma unroll
-        for (int c = j + 1; c < M2; ++c) row[c] -= lj * bcast(lj, c);
+        for (int c = j + 1; c < M2; ++c) row[c] -= lj * sbcast<M2>(lj, base, c);
     }
     if constexpr (Whitener<M2>::kInverse) {
         // lane i: row i of L^{-1}, the forward substitution of the unit vectors
 #pragma unroll
         for (int v = 0; v < M2; ++v) wh.linv[v] = i == v ? 1.f : 0.f;
-        w_forward<M2, M2>(row, invd, wh.linv, i);
+        w_forward<M2, M2>(row, invd, wh.linv, i, base);
     }
     const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m);
     const float nq = (float)n[pix];
@@ -1114,27 +1125,29 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
         float b[1];
         float jc[2 * K];
         w_residual<K>(zp, h2, i, m, T, tt, aa, on, b[0], jc);
-        wh.apply(b, i);
-        return nq * wave_sum_f(b[0] * b[0]);
+        wh.apply(b, i, base);
+        return nq * seg_sum<M2>(b[0] * b[0]);
     };
     float loss = loss_at(tk, ak);
     float mu = 1e-3f;
-    if (any) {
+    {
+        // every segment runs all steps (a pixel without active points has a zero Jacobian: its
+        // step is zero and never kept)
         for (int it = 0; it < witers; ++it) {
             float b[1 + 2 * K];
             float jc[2 * K];
             w_residual<K>(zp, h2, i, m, T, tk, ak, on, b[0], jc);
 #pragma unroll
             for (int c = 0; c < 2 * K; ++c) b[1 + c] = jc[c];
-            wh.apply(b, i);
-            // normal equations (identical in every lane)
+            wh.apply(b, i, base);
+            // normal equations (identical in every lane of the segment)
             float Am[2 * K][2 * K], g[2 * K];
 #pragma unroll
             for (int p = 0; p < 2 * K; ++p) {
-                g[p] = wave_sum_f(b[1 + p] * b[0]);
+                g[p] = seg_sum<M2>(b[1 + p] * b[0]);
 #pragma unroll
                 for (int q = 0; q <= p; ++q) {
-                    Am[p][q] = wave_sum_f(b[1 + p] * b[1 + q]);
+                    Am[p][q] = seg_sum<M2>(b[1 + p] * b[1 + q]);
                     Am[q][p] = Am[p][q];
                 }
             }
@@ -1889,9 +1902,9 @@ hipError_t launch_wsmle(const srt3d_params& p, const double* irf, int irf_len, i
     hipLaunchKernelGGL(spectrum_kernel, dim3(1), dim3(1024), 0, s, irf, irf_len, irf_origin, p.T, 2 * p.m, h2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 grid((unsigned)((A.P + 3) / 4));
 #define SRT3D_WSMLE(M2_)                                                                                            \
-    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((wsmle_kernel<KK, M2_>), grid, dim3(256), 0, s, A, witers, z, n, h2,    \
+    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((wsmle_kernel<KK, M2_>), dim3((unsigned)((A.P + 4 * (64 / M2_) - 1) /    \
+                                           (4 * (64 / M2_)))), dim3(256), 0, s, A, witers, z, n, h2,              \
                                            st.t[half], st.alpha[half], st.active[half], loss))
     if (2 * p.m <= 16) { SRT3D_WSMLE(16); }
     else if (2 * p.m <= 32) { SRT3D_WSMLE(32); }
