@@ -46,6 +46,7 @@ CASES = [
     ("mid", dict(spec=synth.FrameSpec(48, 40, 4096, 8.0, 200.0, 1.0, 1, seed=7), m=16, K=1), 5),
     ("layered", dict(spec=synth.FrameSpec(36, 28, 8192, 8.0, 2000.0, 0.5, 3, seed=5), m=32, K=3), 3),
     ("wide_m", dict(spec=synth.FrameSpec(20, 24, 4096, 6.0, 300.0, 1.0, 1, seed=9), m=48, K=2), 2),
+    ("max_starts", dict(spec=synth.FrameSpec(12, 10, 512, 3.0, 60.0, 1.0, 1, seed=13), m=6, K=1), 64),
 ]
 
 
