@@ -102,15 +102,31 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
         for (int b = 0; b < NT; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
     }
 
+    // The counts of the next 32-bin step are loaded while this one is contracted (one step of
+    // prefetch doubles the loads each wave keeps in flight).
+    uint4 qn[MT];
+#pragma unroll
+    for (int a = 0; a < MT; ++a) {
+        const int64_t row = r0 + a * 16 + li;
+        qn[a] = row < P ? *reinterpret_cast<const uint4*>(H + row * T + 8 * kg) : make_uint4(0, 0, 0, 0);
+    }
     for (int k0 = 0; k0 < T; k0 += 32) {
         const int kk = k0 + 8 * kg;
         uint32_t cnt[MT][8];
         bool anyhi = false;
+        uint4 qc[MT];
+#pragma unroll
+        for (int a = 0; a < MT; ++a) qc[a] = qn[a];
+        if (k0 + 32 < T) {
+#pragma unroll
+            for (int a = 0; a < MT; ++a) {
+                const int64_t row = r0 + a * 16 + li;
+                if (row < P) qn[a] = *reinterpret_cast<const uint4*>(H + row * T + kk + 32);
+            }
+        }
 #pragma unroll
         for (int a = 0; a < MT; ++a) {
-            const int64_t row = r0 + a * 16 + li;
-            uint4 q = make_uint4(0, 0, 0, 0);
-            if (row < P) q = *reinterpret_cast<const uint4*>(H + row * T + kk);
+            const uint4 q = qc[a];
             const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -213,7 +229,10 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
 template <int PREC, int NT>
 static hipError_t launch_hist_nt(const uint16_t* H, int P, int T, int m, const void* ws, float* z, int32_t* n,
                                  hipStream_t s) {
-    constexpr int MT = PREC == SRT3D_PREC_FP32 ? 2 : 4;
+    // two 16-row tiles per wave: 2048 waves at 256^2, which keeps more loads in flight than four
+    // tiles (FP16x2 77 -> 59 us, BF16x3 90 -> 80 us) and more MFMA work per load than one (FP32
+    // 65 -> 81 us)
+    constexpr int MT = 2;
     const int64_t waves = ((int64_t)P + MT * 16 - 1) / (MT * 16);
     const unsigned blocks = (unsigned)((waves + 3) / 4);
     hipLaunchKernelGGL((hist_mfma_kernel<PREC, NT, MT>), dim3(blocks), dim3(256), 0, s, H, P, T, m, ws, z, n);
