@@ -110,6 +110,16 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
         const int64_t row = r0 + a * 16 + li;
         qn[a] = row < P ? *reinterpret_cast<const uint4*>(H + row * T + 8 * kg) : make_uint4(0, 0, 0, 0);
     }
+    float4 fn0[NT], fn1[NT];                           // FP32 form: the next step's F fragments
+    if constexpr (PREC == SRT3D_PREC_FP32) {
+        const float* F = reinterpret_cast<const float*>(ws);
+#pragma unroll
+        for (int b = 0; b < NT; ++b) {
+            const float4* fp = reinterpret_cast<const float4*>(F + (int64_t)(b * 16 + li) * T + 8 * kg);
+            fn0[b] = fp[0];
+            fn1[b] = fp[1];
+        }
+    }
     for (int k0 = 0; k0 < T; k0 += 32) {
         const int kk = k0 + 8 * kg;
         uint32_t cnt[MT][8];
@@ -141,10 +151,23 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
         }
         if constexpr (PREC == SRT3D_PREC_FP32) {
             const float* F = reinterpret_cast<const float*>(ws);
+            float4 fc0[NT], fc1[NT];
 #pragma unroll
             for (int b = 0; b < NT; ++b) {
-                const float4* fp = reinterpret_cast<const float4*>(F + (int64_t)(b * 16 + li) * T + kk);
-                const float4 f0 = fp[0], f1 = fp[1];
+                fc0[b] = fn0[b];
+                fc1[b] = fn1[b];
+            }
+            if (k0 + 32 < T) {
+#pragma unroll
+                for (int b = 0; b < NT; ++b) {
+                    const float4* fp = reinterpret_cast<const float4*>(F + (int64_t)(b * 16 + li) * T + kk + 32);
+                    fn0[b] = fp[0];
+                    fn1[b] = fp[1];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < NT; ++b) {
+                const float4 f0 = fc0[b], f1 = fc1[b];
                 const float fv[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
 #pragma unroll
                 for (int a = 0; a < MT; ++a)
