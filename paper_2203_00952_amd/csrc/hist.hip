@@ -110,6 +110,15 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
         const int64_t row = r0 + a * 16 + li;
         qn[a] = row < P ? *reinterpret_cast<const uint4*>(H + row * T + 8 * kg) : make_uint4(0, 0, 0, 0);
     }
+    uint4 fbn[NT][S];                                  // 16-bit forms: the next step's F fragments
+    if constexpr (PREC != SRT3D_PREC_FP32) {
+        const uint16_t* F = reinterpret_cast<const uint16_t*>(ws);
+#pragma unroll
+        for (int b = 0; b < NT; ++b)
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                fbn[b][s] = *reinterpret_cast<const uint4*>(F + s * plane + (int64_t)(b * 16 + li) * T + 8 * kg);
+    }
     float4 fn0[NT], fn1[NT];                           // FP32 form: the next step's F fragments
     if constexpr (PREC == SRT3D_PREC_FP32) {
         const float* F = reinterpret_cast<const float*>(ws);
@@ -196,11 +205,23 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
                     }
                 }
             }
+            uint4 fc[NT][S];
+#pragma unroll
+            for (int b = 0; b < NT; ++b)
+#pragma unroll
+                for (int s = 0; s < S; ++s) fc[b][s] = fbn[b][s];
+            if (k0 + 32 < T) {
+#pragma unroll
+                for (int b = 0; b < NT; ++b)
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        fbn[b][s] = *reinterpret_cast<const uint4*>(F + s * plane + (int64_t)(b * 16 + li) * T + kk + 32);
+            }
 #pragma unroll
             for (int b = 0; b < NT; ++b) {
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
-                    const v8 fb = *reinterpret_cast<const v8*>(F + s * plane + (int64_t)(b * 16 + li) * T + kk);
+                    const v8 fb = __builtin_bit_cast(v8, fc[b][s]);
 #pragma unroll
                     for (int a = 0; a < MT; ++a) {
                         if constexpr (PREC == SRT3D_PREC_FP16X2)
