@@ -16,8 +16,9 @@
  *    (may be NULL) that the caller zeroes and reads after synchronising:
  *      d_err[0] += number of stamps outside [0, T) (folded by the mathematical modulus),
  *      d_err[1] += number of pixels whose offsets decrease (treated as empty).
- *  - The library keeps no global mutable state; concurrent calls on different streams with
- *    disjoint outputs and workspaces are safe.
+ *  - The library keeps no global mutable state apart from write-once caches of device
+ *    properties (compute-unit counts, kernel occupancies); concurrent calls on different streams
+ *    with disjoint outputs and workspaces are safe.
  *  - Layouts: a sketch is float32 [P][m][2] (real, imaginary interleaved, harmonic l = 1..m
  *    at index l-1), i.e. complex64 [P][m]; pixels are row-major (p = i * cols + j).
  */
@@ -305,12 +306,18 @@ int srt3d_smle_weighted(const float* d_z, const int32_t* d_n, const double* d_ir
                         srt3d_state* st, float* d_loss, void* d_ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------
- * Inspection entry point used to check the exact part of the sketch.
+ * Inspection entry points used to check the exact part of the sketch and every launch form.
  * srt3d_phase_indices: d_k[(l-1) * N + p] = (l * x_p) mod T (mathematical modulus) for
  *   l = 1..m, the integer phase the sketch kernels use; d_x int32 [N], d_k int32 [m * N].
+ * srt3d_sketch_lanes: srt3d_sketch (eq. 3) with the number of lanes that share a pixel fixed
+ *   to `lanes` (4, 8, 16, 32 or 64; anything else is SRT3D_EINVAL) instead of chosen from the
+ *   mean photon count.  Same arguments, outputs and constraints as srt3d_sketch.
  * ------------------------------------------------------------------------------------- */
 int srt3d_phase_indices(const int32_t* d_x, int64_t N, int32_t T, int32_t m, int32_t* d_k,
                         void* stream);
+int srt3d_sketch_lanes(const int32_t* d_stamps, int64_t N, const int64_t* d_offsets, int32_t P,
+                       int32_t T, int32_t m, const float* d_table, float* d_z, int32_t* d_n,
+                       double* d_acc, int64_t* d_nacc, int32_t* d_err, int32_t lanes, void* stream);
 
 const char* srt3d_strerror(int status);
 int srt3d_version(void);

@@ -6,6 +6,7 @@ package is the thin binding plus the serving loop.
 """
 from ._lib import (  # noqa: F401
     EXPORTS,
+    HistWorkspace,
     LIB_PATH,
     PRECISIONS,
     Params,

@@ -46,6 +46,7 @@ _SIGS = {
     "srt3d_phase_table": (_I32, [_I32, _VP, _VP]),
     "srt3d_sketch": (_I32, [_VP, _I64, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "srt3d_sketch_binned": (_I32, [_VP, _I64, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "srt3d_sketch_lanes": (_I32, [_VP, _I64, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _I32, _VP]),
     "srt3d_sketch_events_workspace_bytes": (_SZ, [_I64, _I32]),
     "srt3d_sketch_events": (_I32, [_VP, _VP, _I64, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ,
                                    _VP]),
@@ -116,6 +117,33 @@ def _ptr(t):
     return ctypes.c_void_p(0) if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _shaped(t: torch.Tensor, shape, dtype, name):
+    """_dev plus an exact shape check: the C ABI takes no output sizes, so a buffer of the wrong
+    shape must be refused here, before a kernel writes past its end."""
+    if not isinstance(t, torch.Tensor) or tuple(t.shape) != tuple(shape):
+        got = tuple(t.shape) if isinstance(t, torch.Tensor) else type(t).__name__
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {got}")
+    return _dev(t, dtype, name)
+
+
+def _sketch_outputs(P, m, dev, z, n, acc, nacc, err):
+    """Allocate or check the sketch outputs and the optional long-exposure accumulators."""
+    z = torch.empty((P, m, 2), dtype=torch.float32, device=dev) if z is None else z
+    n = torch.empty(P, dtype=torch.int32, device=dev) if n is None else n
+    _shaped(z, (P, m, 2), torch.float32, "z")
+    _shaped(n, (P,), torch.int32, "n")
+    if (acc is None) != (nacc is None):
+        raise ValueError("acc and nacc are given together or not at all")
+    if acc is not None:
+        _shaped(acc, (P, m, 2), torch.float64, "acc")
+        _shaped(nacc, (P,), torch.int64, "nacc")
+    if err is not None:
+        if err.numel() < 2:
+            raise ValueError("err must hold at least 2 counters")
+        _dev(err, torch.int32, "err")
+    return z, n
+
+
 def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
@@ -157,35 +185,39 @@ def sketch_route(N: int, P: int, T: int, m: int) -> str:
 
 
 def sketch(stamps: torch.Tensor, offsets: torch.Tensor, T: int, m: int, *, acc=None, nacc=None, err=None,
-           z=None, n=None, table=None, method: str = "photon"):
+           z=None, n=None, table=None, method: str = "photon", lanes: int = 0):
     """Photon sketch (eq. 3).  Returns (z float32 [P, m, 2], n int32 [P]).
 
-    method "photon": photon-parallel pass over the phase table (srt3d_sketch);
+    method "photon": photon-parallel pass over the phase table (srt3d_sketch; `lanes` > 0 fixes
+    the lanes per pixel through srt3d_sketch_lanes);
     method "binned": per-pixel histogram on the FP16 matrix cores (srt3d_sketch_binned, m <= 32);
     method "auto": the faster of the two for the frame's photons per pixel (sketch_route)."""
     if method not in SKETCH_METHODS:
         raise ValueError(f"sketch: unknown method {method!r}")
+    if offsets.dim() != 1 or offsets.numel() < 2:
+        raise ValueError("offsets must be [P + 1] with P >= 1")
     P = offsets.numel() - 1
     if method == "auto":
         method = sketch_route(stamps.numel(), P, T, m)
+    if lanes and method != "photon":
+        raise ValueError("lanes applies to the photon pass only")
     dev = offsets.device
     ps = _dev(stamps, torch.int32, "stamps")
     po = _dev(offsets, torch.int64, "offsets")
-    z = torch.empty((P, m, 2), dtype=torch.float32, device=dev) if z is None else z
-    n = torch.empty(P, dtype=torch.int32, device=dev) if n is None else n
-    if acc is not None:
-        _dev(acc, torch.float64, "acc")
-        _dev(nacc, torch.int64, "nacc")
-    if err is not None:
-        _dev(err, torch.int32, "err")
+    z, n = _sketch_outputs(P, m, dev, z, n, acc, nacc, err)
     if table is None:
         if not (2 <= T and T * 8 <= 65536):
             raise ValueError("sketch: invalid T")
         table = cached_phase_table(T, dev)
-    name = "srt3d_sketch" if method == "photon" else "srt3d_sketch_binned"
-    _check(getattr(_lib(), name)(ps, stamps.numel(), po, P, T, m, _dev(table, torch.float32, "table"),
-                                 _dev(z, torch.float32, "z"), _dev(n, torch.int32, "n"), _ptr(acc), _ptr(nacc),
-                                 _ptr(err), _stream(dev)), name)
+    else:
+        _shaped(table, (T, 2), torch.float32, "table")
+    args = (ps, stamps.numel(), po, P, T, m, _dev(table, torch.float32, "table"), _dev(z, torch.float32, "z"),
+            _dev(n, torch.int32, "n"), _ptr(acc), _ptr(nacc), _ptr(err))
+    if lanes:
+        _check(_lib().srt3d_sketch_lanes(*args, int(lanes), _stream(dev)), "srt3d_sketch_lanes")
+    else:
+        name = "srt3d_sketch" if method == "photon" else "srt3d_sketch_binned"
+        _check(getattr(_lib(), name)(*args, _stream(dev)), name)
     return z, n
 
 
@@ -207,17 +239,13 @@ def sketch_events(pix: torch.Tensor, stamps: torch.Tensor, P: int, T: int, m: in
         raise ValueError("sketch_events: pix and stamps differ in length")
     pp = _dev(pix, torch.int32, "pix")
     ps = _dev(stamps, torch.int32, "stamps")
-    z = torch.empty((P, m, 2), dtype=torch.float32, device=dev) if z is None else z
-    n = torch.empty(P, dtype=torch.int32, device=dev) if n is None else n
-    if acc is not None:
-        _dev(acc, torch.float64, "acc")
-        _dev(nacc, torch.int64, "nacc")
-    if err is not None:
-        _dev(err, torch.int32, "err")
+    z, n = _sketch_outputs(P, m, dev, z, n, acc, nacc, err)
     if table is None:
         if not (2 <= T and T * 8 <= 65536):
             raise ValueError("sketch_events: invalid T")
         table = cached_phase_table(T, dev)
+    else:
+        _shaped(table, (T, 2), torch.float32, "table")
     if workspace is None:
         workspace = events_workspace(N, P, dev)
     _dev(workspace, torch.uint8, "workspace")
@@ -228,9 +256,19 @@ def sketch_events(pix: torch.Tensor, stamps: torch.Tensor, P: int, T: int, m: in
     return z, n
 
 
-def hist_workspace(T: int, m: int, precision: str, device) -> torch.Tensor:
+class HistWorkspace:
+    """The DFT matrix prepared by srt3d_hist_prepare for one (T, m, precision); the histogram
+    sketch refuses a workspace prepared for another shape or precision."""
+
+    def __init__(self, T: int, m: int, precision: str, buffer: torch.Tensor):
+        self.T, self.m, self.precision, self.buffer = T, m, precision, buffer
+
+
+def hist_workspace(T: int, m: int, precision: str, device) -> HistWorkspace:
     """The prepared DFT matrix for (T, m, precision) on `device` (built once, then cached)."""
     device = torch.device(device)
+    if precision not in PRECISIONS:
+        raise ValueError(f"unknown precision {precision!r}")
     prec = PRECISIONS[precision]
     key = (device.index if device.index is not None else torch.cuda.current_device(), T, m, prec)
     if key not in _DFT:
@@ -240,7 +278,7 @@ def hist_workspace(T: int, m: int, precision: str, device) -> torch.Tensor:
         ws = _workspace(nbytes, device)
         _check(_lib().srt3d_hist_prepare(T, m, prec, _ptr(ws), ws.numel(), _stream(device)), "srt3d_hist_prepare")
         torch.cuda.current_stream(device).synchronize()
-        _DFT[key] = ws
+        _DFT[key] = HistWorkspace(T, m, precision, ws)
     return _DFT[key]
 
 
@@ -253,11 +291,16 @@ def sketch_from_hist(hist: torch.Tensor, m: int, precision: str = "fp32", *, z=N
     if hist.dtype not in (torch.int16, torch.uint16):
         raise TypeError("hist must be int16 (uint16 bits) or uint16")
     ph = _dev(hist, hist.dtype, "hist")
+    if precision not in PRECISIONS:
+        raise ValueError(f"unknown precision {precision!r}")
     prec = PRECISIONS[precision]
-    z = torch.empty((P, m, 2), dtype=torch.float32, device=dev) if z is None else z
-    n = torch.empty(P, dtype=torch.int32, device=dev) if n is None else n
+    z, n = _sketch_outputs(P, m, dev, z, n, None, None, None)
     ws = hist_workspace(T, m, precision, dev) if workspace is None else workspace
-    _check(_lib().srt3d_sketch_from_hist(ph, P, T, m, prec, _ptr(ws), ws.numel(), _dev(z, torch.float32, "z"),
+    if not isinstance(ws, HistWorkspace) or (ws.T, ws.m, ws.precision) != (T, m, precision):
+        raise ValueError("sketch_from_hist: workspace was not prepared for this T, m and precision")
+    buf = ws.buffer
+    _dev(buf, torch.uint8, "workspace")
+    _check(_lib().srt3d_sketch_from_hist(ph, P, T, m, prec, _ptr(buf), buf.numel(), _dev(z, torch.float32, "z"),
                                          _dev(n, torch.int32, "n"), _stream(dev)), "srt3d_sketch_from_hist")
     return z, n
 

@@ -41,6 +41,30 @@ int check_state(const srt3d_state* st) {
 
 }  // namespace
 
+namespace srt3d {
+
+hipError_t current_device_cus(int* cus) {
+    static std::atomic<int> cache[kMaxDevices];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev >= 0 && dev < kMaxDevices) {
+        const int v = cache[dev].load(std::memory_order_relaxed);
+        if (v > 0) {
+            *cus = v;
+            return hipSuccess;
+        }
+    }
+    int v = 0;
+    if ((e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if (v < 1) v = 1;
+    if (dev >= 0 && dev < kMaxDevices) cache[dev].store(v, std::memory_order_relaxed);
+    *cus = v;
+    return hipSuccess;
+}
+
+}  // namespace srt3d
+
 extern "C" {
 
 void srt3d_params_default(srt3d_params* p, int32_t rows, int32_t cols, int32_t T, int32_t m, int32_t K_max) {
@@ -72,6 +96,18 @@ int srt3d_sketch(const int32_t* d_stamps, int64_t N, const int64_t* d_offsets, i
     if (!aligned(d_table, 8) || !aligned(d_z, 8)) return SRT3D_EINVAL;
     return dev_status(launch_sketch_photons(d_stamps, N, d_offsets, P, T, m, reinterpret_cast<const float2*>(d_table),
                                             d_z, d_n, d_acc, d_nacc, d_err, as_stream(stream)));
+}
+
+int srt3d_sketch_lanes(const int32_t* d_stamps, int64_t N, const int64_t* d_offsets, int32_t P, int32_t T, int32_t m,
+                       const float* d_table, float* d_z, int32_t* d_n, double* d_acc, int64_t* d_nacc, int32_t* d_err,
+                       int32_t lanes, void* stream) {
+    if (lanes != 4 && lanes != 8 && lanes != 16 && lanes != 32 && lanes != 64) return SRT3D_EINVAL;
+    if (P < 1 || N < 0 || !sketch_dims_ok(T, m)) return SRT3D_EINVAL;
+    if ((!d_stamps && N > 0) || !d_offsets || !d_table || !d_z || !d_n) return SRT3D_EINVAL;
+    if ((d_acc == nullptr) != (d_nacc == nullptr)) return SRT3D_EINVAL;
+    if (!aligned(d_table, 8) || !aligned(d_z, 8)) return SRT3D_EINVAL;
+    return dev_status(launch_sketch_photons(d_stamps, N, d_offsets, P, T, m, reinterpret_cast<const float2*>(d_table),
+                                            d_z, d_n, d_acc, d_nacc, d_err, as_stream(stream), lanes));
 }
 
 int srt3d_sketch_binned(const int32_t* d_stamps, int64_t N, const int64_t* d_offsets, int32_t P, int32_t T,

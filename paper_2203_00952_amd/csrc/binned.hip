@@ -435,14 +435,11 @@ template <int Q, int MTT, int U>
 hipError_t launch_binned(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T, int m,
                          const float2* table, float* z, int32_t* n, double* acc, int64_t* nacc, int32_t* err,
                          hipStream_t s) {
-    int dev = 0, cus = 0, per_cu = 0;
-    hipError_t st = hipGetDevice(&dev);
+    int cus = 0, per_cu = 0;
+    hipError_t st = current_device_cus(&cus);
     if (st != hipSuccess) return st;
-    st = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    st = cached_occupancy<sketch_binned_kernel<Q, MTT, U>, kBinThreads>(&per_cu);
     if (st != hipSuccess) return st;
-    st = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sketch_binned_kernel<Q, MTT, U>, kBinThreads, 0);
-    if (st != hipSuccess) return st;
-    if (per_cu < 1) per_cu = 1;
     const int64_t cap = (int64_t)cus * per_cu;
     const int64_t need = ((int64_t)P + kBinWaves - 1) / kBinWaves;
     const unsigned blocks = (unsigned)(need < cap ? need : cap);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "srt3d.h"
 
 namespace srt3d {
@@ -42,12 +44,44 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Device properties the launch shapes depend on, queried once per device and kept for the life of
+// the process (write-once caches: concurrent first calls store the same value).
+constexpr int kMaxDevices = 64;
+
+// Compute units of the current device.
+hipError_t current_device_cus(int* cus);
+
+// Resident workgroups per compute unit of `Kernel` launched with `Threads` threads and no dynamic
+// LDS, on the current device (at least 1).
+template <auto Kernel, int Threads>
+hipError_t cached_occupancy(int* per_cu) {
+    static std::atomic<int> cache[kMaxDevices];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev >= 0 && dev < kMaxDevices) {
+        const int v = cache[dev].load(std::memory_order_relaxed);
+        if (v > 0) {
+            *per_cu = v;
+            return hipSuccess;
+        }
+    }
+    int v = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, Kernel, Threads, 0);
+    if (e != hipSuccess) return e;
+    if (v < 1) v = 1;
+    if (dev >= 0 && dev < kMaxDevices) cache[dev].store(v, std::memory_order_relaxed);
+    *per_cu = v;
+    return hipSuccess;
+}
+
 // Launch wrappers (defined in the .hip files).  All return hipSuccess or the launch error.
 hipError_t launch_phase_table(int T, float2* table, hipStream_t s);
 hipError_t launch_phase_indices(const int32_t* x, int64_t N, int T, int m, int32_t* k, hipStream_t s);
+// lanes: lanes per pixel (4, 8, 16, 32 or 64), 0 = chosen from the mean photon count
 hipError_t launch_sketch_photons(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T,
                                  int m, const float2* table, float* z, int32_t* n, double* acc,
-                                 int64_t* nacc, int32_t* err, hipStream_t s);
+                                 int64_t* nacc, int32_t* err, hipStream_t s, int lanes = 0);
 hipError_t launch_sketch_binned(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T,
                                 int m, const float2* table, float* z, int32_t* n, double* acc,
                                 int64_t* nacc, int32_t* err, hipStream_t s);

@@ -4,10 +4,18 @@
 // that S is already in the [P][m][2] sketch layout).  This is a dense contraction, so it runs on
 // the matrix cores:
 //  * FP32:   v_mfma_f32_16x16x4_f32 on FP32 counts (exact) and FP32-rounded F.
-//  * FP16X2: counts split exactly as H = 2^11 hi + lo (both exact in FP16), F = F1 + F2 with
+//  * FP16X2: counts split exactly into hi + lo (s = 11, both exact in FP16), F = F1 + F2 with
 //            F1 = fp16(F), F2 = fp16(F - F1); v_mfma_f32_16x16x32_f16, FP32 accumulation.
-//  * BF16X3: H = 2^8 hi + lo (exact in BF16), F = F1 + F2 + F3 in BF16; v_mfma_f32_16x16x32_bf16.
-//  The hi products run only for k-chunks where some count in the wave's rows reaches 2^s.
+//  * BF16X3: counts split into hi + lo (s = 8, exact in BF16), F = F1 + F2 + F3 in BF16;
+//            v_mfma_f32_16x16x32_bf16.
+//  The hi products run only for k-chunks where some reduced count in the wave's rows reaches 2^s
+//  in magnitude.
+// Before the product every count of a row is reduced by a constant c of that row (the rounded
+// mean of its first 32 bins, at most 2^15): sum_t exp(i w_l t) over all T bins is zero for
+// 0 < l < T, so S is unchanged in exact arithmetic, while the FP32 partial sums of a row with a
+// high common level (a constant row sketches to exactly zero) stay at the scale of the
+// deviations.  The reduced counts d lie in [-2^15, 2^16) and split exactly: d itself when
+// |d| < 2^s, else a multiple of 2^s plus a remainder in [0, 2^s).
 // A operands come straight from HBM into registers (each lane loads 8 consecutive counts of one
 // row, 16 B, which is exactly its slice of a 16x32 A tile); F is small and stays in L2.  The
 // 16-bit A tile for FP32 uses the same 8 counts over 8 MFMAs with K = 4 (k order is immaterial
@@ -129,9 +137,24 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
             fn1[b] = fp[1];
         }
     }
+    // Per-row level c: rounded mean of the row's first 32 bins (the four lanes of a row hold
+    // eight bins each), capped at 2^15 so that every reduced count splits exactly.
+    int32_t lvl[MT];
+#pragma unroll
+    for (int a = 0; a < MT; ++a) {
+        const uint4 q = qn[a];
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+        uint32_t s8 = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s8 += (w[j] & 0xffffu) + (w[j] >> 16);
+        s8 += __shfl_xor(s8, 16, 64);
+        s8 += __shfl_xor(s8, 32, 64);
+        const uint32_t c = (s8 + 16u) >> 5;
+        lvl[a] = (int32_t)(c < 32768u ? c : 32768u);
+    }
     for (int k0 = 0; k0 < T; k0 += 32) {
         const int kk = k0 + 8 * kg;
-        uint32_t cnt[MT][8];
+        int32_t cnt[MT][8];
         bool anyhi = false;
         uint4 qc[MT];
 #pragma unroll
@@ -149,13 +172,16 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
             const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                cnt[a][2 * j] = w[j] & 0xffffu;
-                cnt[a][2 * j + 1] = w[j] >> 16;
+                rsum[a] += (w[j] & 0xffffu) + (w[j] >> 16);
+                cnt[a][2 * j] = (int32_t)(w[j] & 0xffffu) - lvl[a];
+                cnt[a][2 * j + 1] = (int32_t)(w[j] >> 16) - lvl[a];
             }
+            if constexpr (PREC != SRT3D_PREC_FP32) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                rsum[a] += cnt[a][j];
-                if constexpr (PREC != SRT3D_PREC_FP32) anyhi |= (cnt[a][j] >> Prec<PREC>::shift) != 0;
+                for (int j = 0; j < 8; ++j) {
+                    const int32_t d = cnt[a][j];
+                    anyhi |= (d < 0 ? -d : d) >= (1 << Prec<PREC>::shift);
+                }
             }
         }
         if constexpr (PREC == SRT3D_PREC_FP32) {
@@ -194,8 +220,12 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
             for (int a = 0; a < MT; ++a) {
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    const uint32_t lo = cnt[a][j] & ((1u << SH) - 1u);
-                    const uint32_t hi = (cnt[a][j] >> SH) << SH;
+                    // d = hi + lo, both exact in the 16-bit format: hi = 0 when |d| < 2^SH,
+                    // else hi = d rounded down to a multiple of 2^SH (in [-2^15, 2^16)) and
+                    // lo in [0, 2^SH)
+                    const int32_t d = cnt[a][j];
+                    const int32_t hi = (d < 0 ? -d : d) < (1 << SH) ? 0 : (d & ~((1 << SH) - 1));
+                    const int32_t lo = d - hi;
                     if constexpr (PREC == SRT3D_PREC_FP16X2) {
                         alo[a][j] = (_Float16)(float)lo;
                         ahi[a][j] = (_Float16)(float)hi;

@@ -262,15 +262,12 @@ template <int G, bool POW2, int TB, int MCMAX>
 static hipError_t launch_sketch_g(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T, int m,
                                   const float2* table, float* z, int32_t* n, double* acc, int64_t* nacc,
                                   int32_t* err, hipStream_t s) {
-    const int threads = 256;
-    int dev = 0, cus = 0, per_cu = 0;
-    hipError_t st = hipGetDevice(&dev);
+    constexpr int threads = 256;
+    int cus = 0, per_cu = 0;
+    hipError_t st = current_device_cus(&cus);
     if (st != hipSuccess) return st;
-    st = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    st = cached_occupancy<sketch_photons_kernel<G, POW2, TB, MCMAX>, threads>(&per_cu);
     if (st != hipSuccess) return st;
-    st = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sketch_photons_kernel<G, POW2, TB, MCMAX>, threads, 0);
-    if (st != hipSuccess) return st;
-    if (per_cu < 1) per_cu = 1;
     const int64_t groups_per_block = threads / G;
     const int64_t need = ((int64_t)P + groups_per_block - 1) / groups_per_block;
     const int64_t cap = (int64_t)cus * per_cu;
@@ -307,10 +304,9 @@ static int lanes_per_pixel(int64_t N, int P) {
 
 hipError_t launch_sketch_photons(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T, int m,
                                  const float2* table, float* z, int32_t* n, double* acc, int64_t* nacc,
-                                 int32_t* err, hipStream_t s) {
+                                 int32_t* err, hipStream_t s, int lanes) {
     const bool pow2 = (T & (T - 1)) == 0;
-    const char* env = getenv("SRT3D_SKETCH_LANES");
-    const int G = env ? atoi(env) : lanes_per_pixel(N, P);
+    const int G = lanes > 0 ? lanes : lanes_per_pixel(N, P);
 #define SRT3D_SK(GG)                                                                                              \
     return pow2 ? launch_sketch_tb<GG, true>(stamps, N, offsets, P, T, m, table, z, n, acc, nacc, err, s)         \
                 : launch_sketch_tb<GG, false>(stamps, N, offsets, P, T, m, table, z, n, acc, nacc, err, s)

@@ -1835,9 +1835,8 @@ hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int 
                        EB, rho, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    int dev = 0, cus = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    int cus = 0;
+    if ((e = current_device_cus(&cus)) != hipSuccess) return e;
     int64_t blocks = ((int64_t)(P + 15) / 16 + 3) / 4;
     const int64_t cap = std::min<int64_t>((int64_t)cus * 8, kInitBlocksMax);
     if (blocks > cap) blocks = cap;

@@ -3,11 +3,12 @@
 Section 2, eq. (1): each photon of a pixel comes from surface k with
 probability alpha_k (its stamp is the surface depth t_k plus a draw from the
 impulse response h) or from the background with probability alpha_0 (its stamp
-is uniform on {0, ..., T-1}).  Section 4 synthesises frames "for different mean
-photons per pixel n and SBR levels" from a reference depth map; the real
-reference scenes are not available, so `make_scene` draws piecewise-planar
-scenes instead (a back wall, three axis-aligned objects and, for layered
-frames, a front mesh with partial coverage).
+is uniform on {0, ..., T-1}).  Section 4 builds its synthetic frames from a
+reference depth map at a range of mean photon counts per pixel and of
+signal-to-background ratios; the reference scenes are not available, so
+`make_scene` draws piecewise-planar scenes instead (a back wall, three
+axis-aligned objects and, for layered frames, a front mesh with partial
+coverage).
 
 Scene geometry is drawn with numpy's PCG64 from `seed`; photons are drawn with a
 torch generator on the requested device (seed + 1), so large frames are
@@ -178,8 +179,9 @@ def draw_photons(spec: FrameSpec, scene: Scene, device="cpu"):
     """Poisson photon counts per surface and per-photon stamps, pixel-major CSR.
 
     A signal stamp is round(t_k + sigma*N(0,1)) mod T, a background stamp is
-    uniform on {0..T-1}.  Within a pixel the stamps are grouped by source
-    (surfaces first, then background); eq. (3) is a sum, so order is immaterial.
+    uniform on {0..T-1}.  Within a pixel the stamps are in random order (a
+    detector records a pixel's signal and background photons interleaved), by a
+    sort on (pixel, random key).
     """
     device = torch.device(device)
     sig_mean, bg_mean = expected_counts(spec, scene)
@@ -203,8 +205,12 @@ def draw_photons(spec: FrameSpec, scene: Scene, device="cpu"):
         noise = torch.randn(src.numel(), generator=gen, device=device, dtype=torch.float32)
         bg = torch.randint(0, T, (src.numel(),), generator=gen, device=device, dtype=torch.int64)
         sig = torch.remainder(torch.round(d + spec.sigma * noise).to(torch.int64), T)
-        parts.append(torch.where(is_sig, sig, bg).to(torch.int32))
-        del src, comp, pix, is_sig, d, noise, bg, sig
+        st = torch.where(is_sig, sig, bg).to(torch.int32)
+        del src, comp, is_sig, d, noise, bg, sig
+        key = torch.randint(0, 1 << 31, (st.numel(),), generator=gen, device=device, dtype=torch.int64)
+        order = torch.argsort(pix * (1 << 31) + key)
+        parts.append(st[order])
+        del pix, key, order, st
     stamps = torch.cat(parts) if parts else torch.empty(0, dtype=torch.int32, device=device)
     n = counts.sum(1)
     offsets = torch.zeros(P + 1, dtype=torch.int64, device=device)

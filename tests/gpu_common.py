@@ -16,14 +16,12 @@ def to_complex(z: torch.Tensor) -> np.ndarray:
     return a[..., 0] + 1j * a[..., 1]
 
 
-def sketch_violations(z_gpu: np.ndarray, z_ref: np.ndarray, n: np.ndarray, abs_floor: float = 0.0):
+def sketch_violations(z_gpu: np.ndarray, z_ref: np.ndarray, n: np.ndarray):
     """Entries breaking the sketch rule.  The floor n^-1/2 is the spread of the empirical
-    characteristic function (eq. 5); a pixel with n = 0 must be exactly zero.  `abs_floor`
-    is an optional absolute tolerance for cases whose n is so large that 1e-5 n^-1/2 falls
-    below FP32's own rounding of the sums."""
+    characteristic function (eq. 5); a pixel with n = 0 must be exactly zero."""
     n = np.asarray(n, dtype=np.float64)
     floor = np.where(n > 0, 1.0 / np.sqrt(np.maximum(n, 1.0)), 0.0)[:, None]
-    tol = np.maximum(SKETCH_REL * np.maximum(np.abs(z_ref), floor), abs_floor)
+    tol = SKETCH_REL * np.maximum(np.abs(z_ref), floor)
     err = np.abs(z_gpu - z_ref)
     bad = err > tol
     bad |= (n[:, None] == 0) & (z_gpu != 0)

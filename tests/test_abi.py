@@ -97,6 +97,12 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.srt3d_sketch_binned(fake, 10, fake, 4, 1024, 4, None, fake, fake, None, None, None, None) == -1
     assert lib.srt3d_sketch_binned(fake, 10, fake, 4, 1024, 4, fake, fake, fake, fake, None, None, None) == -1
     assert lib.srt3d_phase_table(1, fake, None) == -1
+    # fixed lane counts: only 4, 8, 16, 32 and 64, and the sketch's own checks
+    for lanes in (0, 3, 5, 12, 128, -4):
+        assert lib.srt3d_sketch_lanes(fake, 10, fake, 4, 1024, 4, fake, fake, fake, None, None, None, lanes,
+                                      None) == -1
+    assert lib.srt3d_sketch_lanes(fake, 10, fake, 4, 1024, 513, fake, fake, fake, None, None, None, 16, None) == -1
+    assert lib.srt3d_sketch_lanes(fake, 10, fake, 4, 1024, 4, fake, None, fake, None, None, None, 16, None) == -1
     # event streams: P < 1, m > T/2, NULL pixels with events, NULL workspace, misaligned or too
     # small workspace, N or P past the limits
     ws = VP(0x10000)

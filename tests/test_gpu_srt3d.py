@@ -211,12 +211,15 @@ def test_end_to_end_tiny_with_independent_oracle_sketch():
     np.testing.assert_allclose(out["bg"].cpu().numpy(), r["bg"], rtol=1e-3, atol=1e-6)
 
 
-def test_end_to_end_throughput_frame():
-    """256x256, T=4096, m=16, 50 iterations: GPU reconstruct vs oracle reconstruct of the same sketch."""
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", ["throughput", "throughput_sbr0.1", "throughput_sbr10"])
+def test_end_to_end_throughput_frame(name):
+    """256x256, T=4096, m=16, 50 iterations at SBR 1, 0.1 and 10: GPU reconstruct vs oracle
+    reconstruct of the same sketch."""
     dev = device()
-    w = synth.preset("throughput")
+    w = synth.preset(name)
     fr = Frame(w.frame, w.m, w.K_max, dev)
-    _case(test="e2e_throughput")
+    _case(test="e2e_throughput", preset=name)
     out = fr.rec.reconstruct(fr.z, fr.n, fr.irf, fr.f.irf_origin)
     torch.cuda.synchronize()
     r = O.reconstruct(fr.zc, fr.nn, fr.f.irf, fr.f.irf_origin, fr.spec.rows, fr.spec.cols, fr.op)
@@ -228,16 +231,52 @@ def test_end_to_end_throughput_frame():
     print("median |depth - truth| (bins):", float(np.median(err)))
 
 
-def test_end_to_end_layered():
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["tiny", "throughput"])
+def test_end_to_end_binned_pipeline(name):
+    """Exactly the timed pipeline of the benchmark -- the binned sketch of the stamps, then
+    srt3d_reconstruct -- against the oracle's own FP64 sketch of the same stamps followed by the
+    oracle's reconstruction."""
     dev = device()
-    fr = layered(dev)
-    _case(test="e2e_layered")
+    w = synth.preset(name)
+    spec = w.frame
+    f = synth.make_frame(spec, device=dev)
+    _case(test="e2e_binned_pipeline", preset=name, photons=f.stamps.numel())
+    z, n = srt.sketch(f.stamps, f.offsets, spec.T, w.m, method="binned")
+    params = srt.Params.default(spec.rows, spec.cols, spec.T, w.m, w.K_max, iters=w.iters, r_min=w.r_min)
+    rec = srt.Reconstructor(params, dev)
+    out = rec.reconstruct(z, n, torch.from_numpy(f.irf).to(dev), f.irf_origin)
+    torch.cuda.synchronize()
+    z_ref, n_ref = OS.sketch(f.stamps.cpu().numpy(), f.offsets.cpu().numpy(), spec.T, w.m)
+    np.testing.assert_array_equal(n.cpu().numpy(), n_ref)
+    op = O.Params(spec.T, w.m, w.K_max, iters=w.iters, r_min=w.r_min)
+    r = O.reconstruct(z_ref, n_ref, f.irf, f.irf_origin, spec.rows, spec.cols, op)
+    ok = pixel_pass(out["depth"].cpu().numpy(), out["active"].cpu().numpy(), r["depth"], r["active"], spec.T)
+    print(name, "binned sketch -> reconstruct vs oracle: pixels within 1 bin", ok.mean(), "failing",
+          int((~ok).sum()))
+    assert ok.mean() >= 0.999
+    bg_g = out["bg"].cpu().numpy()
+    bg_ok = np.abs(bg_g - r["bg"]) <= 1e-3 * np.abs(r["bg"]) + 1e-6
+    print("background within 1e-3 relative:", bg_ok.mean())
+    assert bg_ok.mean() >= 0.999
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("size", [(48, 40), (128, 128)])
+def test_end_to_end_layered(size):
+    """Layered frames with the 1.05e9-photon frame's statistics (T = 8192, up to 3 surfaces per
+    pixel, ~4000 photons per pixel, SBR 0.5, m = 32, K_max = 3) on crops the oracle finishes in
+    a test: 50 iterations end to end."""
+    dev = device()
+    fr = layered(dev, rows=size[0], cols=size[1])
+    _case(test="e2e_layered", rows=size[0], cols=size[1], iters=fr.params.iters)
     out = fr.rec.reconstruct(fr.z, fr.n, fr.irf, fr.f.irf_origin)
     torch.cuda.synchronize()
     r = O.reconstruct(fr.zc, fr.nn, fr.f.irf, fr.f.irf_origin, fr.spec.rows, fr.spec.cols, fr.op)
     ok = pixel_pass(out["depth"].cpu().numpy(), out["active"].cpu().numpy(), r["depth"], r["active"], fr.spec.T)
-    print("layered end to end: pixels within 1 bin", ok.mean(), "failing", int((~ok).sum()))
-    assert ok.mean() >= 0.995
+    print("layered end to end: pixels within 1 bin", ok.mean(), "failing", int((~ok).sum()),
+          "points per pixel (oracle)", np.bincount(r["active"].sum(1), minlength=4) / fr.spec.P)
+    assert ok.mean() >= 0.999
 
 
 def test_end_to_end_camouflage():
@@ -252,7 +291,7 @@ def test_end_to_end_camouflage():
     r = O.reconstruct(fr.zc, fr.nn, fr.f.irf, fr.f.irf_origin, fr.spec.rows, fr.spec.cols, fr.op)
     ok = pixel_pass(out["depth"].cpu().numpy(), out["active"].cpu().numpy(), r["depth"], r["active"], fr.spec.T)
     print("camouflage end to end: pixels within 1 bin", ok.mean(), "failing", int((~ok).sum()))
-    assert ok.mean() >= 0.995
+    assert ok.mean() >= 0.999
 
 
 def _camouflage(dev, **pk):
@@ -316,7 +355,7 @@ def test_iterations_with_births_match_oracle():
     two = a.sum(1) == 2
     print("pixels within 1 bin", ok.mean(), "two points (oracle)", two.mean())
     assert two.mean() > 0.8
-    assert ok.mean() >= 0.995
+    assert ok.mean() >= 0.999
 
 
 def test_deterministic_and_resumable():

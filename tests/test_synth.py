@@ -19,11 +19,16 @@ def test_frame_structure_and_statistics():
     sig = f.counts[:, :-1].sum().item()
     bg = f.counts[:, -1].sum().item()
     assert abs(sig / bg - 1.0) < 0.03
-    # signal stamps cluster around the depth of their pixel
+    # signal stamps cluster around the depth of their pixel, interleaved with the background
     p = int(np.argmax(n))
-    x = f.stamps[f.offsets[p]:f.offsets[p] + f.counts[p, 0]].numpy()
+    x = f.stamps[f.offsets[p]:f.offsets[p + 1]].numpy()
     d = (x - f.scene.depth[p, 0] + spec.T / 2) % spec.T - spec.T / 2
-    assert abs(np.median(d)) < 3 and np.std(d) < 12
+    near = np.abs(d) <= 6 * spec.sigma
+    nsig, nbg = int(f.counts[p, 0]), int(f.counts[p, 1])
+    assert nsig <= near.sum() <= nsig + nbg * (12 * spec.sigma + 1) / spec.T + 5 * np.sqrt(nbg) + 1
+    assert abs(np.median(d[near])) < 3 and np.std(d[near]) < 12
+    first = near[:nsig].mean()
+    assert 0.2 < first < 0.9          # grouped by source would give 1.0
 
 
 def test_reproducible_and_seeded():
