@@ -190,8 +190,12 @@ int srt3d_sketch_events(const int32_t* d_pix, const int32_t* d_stamps, int64_t N
 /* ---------------------------------------------------------------------------------------
  * Sketch of per-pixel ToA histograms -- eq. (2) with unit bins [t, t+1), then eq. (3):
  *     S_l = sum_t H[p][t] exp(i w_l t),  n = sum_t H[p][t],  z = S / n,
- * computed as the product H [P x T] . F [T x 2m] with F the cos/sin DFT columns.
- * srt3d_hist_prepare writes F (split for the chosen precision) into d_ws, of
+ * computed as the product H [P x T] . F [T x 2m] with F the cos/sin DFT columns.  Each row is
+ * taken in chunks of 32 bins; the chunk's rounded mean count c_k is removed from its counts
+ * before the product and added back as sum_k c_k G_k with G_k the sum of F over the chunk (exact
+ * integers times FP64 G on the FP64 matrix cores), so the FP32 accumulation only sees
+ * deviations from a local level.
+ * srt3d_hist_prepare writes F (split for the chosen precision) and G (FP64) into d_ws, of
  * srt3d_hist_workspace_bytes(T, m, precision) bytes; build it once per (T, m, precision).
  * srt3d_sketch_from_hist is then one kernel launch:
  *   d_hist    uint16 [P][T] row-major counts, 16-byte aligned

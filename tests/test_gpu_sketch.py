@@ -185,10 +185,11 @@ def test_hist_sketch_matches_oracle(precision, m):
 @pytest.mark.parametrize("precision", ["fp32", "fp16x2", "bf16x3"])
 def test_hist_hi_counts_path(precision):
     """Counts at and above 2^8 / 2^11 exercise the exact hi/lo split of the 16-bit forms, and
-    rows with a high common level exercise the per-row level removed before the product (a
-    constant row sketches to exactly zero; a row whose first bins are high and the rest low
-    gives reduced counts far below zero).  Held to the sketch rule with no absolute floor:
-    these pixels hold up to 6.6e4 counts, where 1e-5 n^-1/2 is below 4e-8."""
+    rows with high levels exercise the per-chunk level removed before the product and added
+    back in FP64 (a constant row sketches to exactly zero; a row whose first 32 bins hold 30000
+    or 65535 counts and the rest near zero has a harmonic at which the block cancels, with n
+    near 2e6, where the rule asks for 7e-9 in z).  Held to the sketch rule with no absolute
+    floor."""
     dev = device()
     rng = np.random.default_rng(4)
     P, T, m = 100, 256, 8
