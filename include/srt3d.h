@@ -38,7 +38,9 @@ enum srt3d_status {
     SRT3D_OK = 0,
     SRT3D_EINVAL = -1,   /* invalid argument (sizes, NULL pointers, parameters) */
     SRT3D_ENOMEM = -2,   /* workspace smaller than the matching *_workspace_bytes */
-    SRT3D_EDEVICE = -3   /* a HIP call failed */
+    SRT3D_EDEVICE = -3,  /* a HIP call failed */
+    SRT3D_ESCRATCH = -4  /* the problem needs more scratch than srt3d_reconstruct_noalloc's
+                            static array holds (SRT3D_STATIC_SCRATCH_BYTES) */
 };
 
 /* Arithmetic of the histogram sketch (srt3d_sketch_from_hist). */
@@ -260,6 +262,24 @@ int srt3d_reconstruct(const float* d_z, const int32_t* d_n, const double* d_irf,
                       int32_t irf_len, int32_t irf_origin, const srt3d_params* p,
                       srt3d_state* st, float* d_depth, float* d_intensity, uint8_t* d_active,
                       float* d_bg, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * srt3d_reconstruct without a workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments (less d_ws, ws_bytes), computation and outputs as srt3d_reconstruct; the
+ * initialisation's scratch lives in a static device array of SRT3D_STATIC_SCRATCH_BYTES bytes
+ * that the library holds on each device it runs on until the process ends.  The call allocates
+ * nothing.  It returns SRT3D_ESCRATCH, before enqueueing anything, when
+ * srt3d_init_workspace_bytes(p) exceeds that size (every configuration with the default
+ * init_stride and T * 8 <= 65536 fits; a small explicit init_stride may not).  Every call on
+ * one device shares that device's array: calls that overlap in time on one device (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * ------------------------------------------------------------------------------------- */
+#define SRT3D_STATIC_SCRATCH_BYTES (1u << 20)
+int srt3d_reconstruct_noalloc(const float* d_z, const int32_t* d_n, const double* d_irf,
+                              int32_t irf_len, int32_t irf_origin, const srt3d_params* p,
+                              srt3d_state* st, float* d_depth, float* d_intensity,
+                              uint8_t* d_active, float* d_bg, void* stream);
 
 /* ---------------------------------------------------------------------------------------
  * Pixelwise sketched estimator -- the comparison system of Sections 1 and 4 (SMLE): each

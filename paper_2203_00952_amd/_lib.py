@@ -15,7 +15,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsrt3d.so")
 
-SRT3D_OK, SRT3D_EINVAL, SRT3D_ENOMEM, SRT3D_EDEVICE = 0, -1, -2, -3
+SRT3D_OK, SRT3D_EINVAL, SRT3D_ENOMEM, SRT3D_EDEVICE, SRT3D_ESCRATCH = 0, -1, -2, -3, -4
+STATIC_SCRATCH_BYTES = 1 << 20
 PRECISIONS = {"fp32": 0, "fp16x2": 1, "bf16x3": 2}
 STAGES = {"data": 0, "depth": 1, "intensity": 2, "birth": 3}
 MAX_M_RECON, MAX_K, MAX_R, NSCAL, MAX_STARTS = 64, 3, 3, 8, 64
@@ -68,6 +69,8 @@ _SIGS = {
     "srt3d_finalize": (_I32, [ctypes.POINTER(_State), _VP, ctypes.POINTER(_Params), _VP, _VP, _VP, _VP, _VP]),
     "srt3d_reconstruct": (_I32, [_VP, _VP, _VP, _I32, _I32, ctypes.POINTER(_Params), ctypes.POINTER(_State),
                                  _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "srt3d_reconstruct_noalloc": (_I32, [_VP, _VP, _VP, _I32, _I32, ctypes.POINTER(_Params), ctypes.POINTER(_State),
+                                         _VP, _VP, _VP, _VP, _VP]),
     "srt3d_phase_indices": (_I32, [_VP, _I64, _I32, _I32, _VP, _VP]),
     "srt3d_strerror": (ctypes.c_char_p, [_I32]),
     "srt3d_version": (_I32, []),
@@ -466,7 +469,10 @@ class Reconstructor:
                                      _stream(self.device)), "srt3d_finalize")
         return out
 
-    def reconstruct(self, z, n, irf, origin: int, out=None):
+    def reconstruct(self, z, n, irf, origin: int, out=None, no_alloc: bool = False):
+        """init + iterate + finalize (srt3d_reconstruct).  With no_alloc=True the call goes to
+        srt3d_reconstruct_noalloc, whose scratch is the library's static device array instead of
+        this object's workspace (given `out`, nothing is allocated on the way)."""
         self._zn(z, n)
         _dev(irf, torch.float64, "irf")
         P, K = self.p.P, self.p.K_max
@@ -475,10 +481,16 @@ class Reconstructor:
                        intensity=torch.empty((P, K), dtype=torch.float32, device=self.device),
                        active=torch.empty((P, K), dtype=torch.uint8, device=self.device),
                        bg=torch.empty(P, dtype=torch.float32, device=self.device))
-        _check(_lib().srt3d_reconstruct(_ptr(z), _ptr(n), _ptr(irf), irf.numel(), origin, ctypes.byref(self._cp),
-                                        ctypes.byref(self._st), _ptr(out["depth"]), _ptr(out["intensity"]),
-                                        _ptr(out["active"]), _ptr(out["bg"]), _ptr(self.ws), self.ws.numel(),
-                                        _stream(self.device)), "srt3d_reconstruct")
+        for k, shape, dt in (("depth", (P, K), torch.float32), ("intensity", (P, K), torch.float32),
+                             ("active", (P, K), torch.uint8), ("bg", (P,), torch.float32)):
+            _shaped(out[k], shape, dt, k)
+        args = (_ptr(z), _ptr(n), _ptr(irf), irf.numel(), origin, ctypes.byref(self._cp), ctypes.byref(self._st),
+                _ptr(out["depth"]), _ptr(out["intensity"]), _ptr(out["active"]), _ptr(out["bg"]))
+        if no_alloc:
+            _check(_lib().srt3d_reconstruct_noalloc(*args, _stream(self.device)), "srt3d_reconstruct_noalloc")
+        else:
+            _check(_lib().srt3d_reconstruct(*args, _ptr(self.ws), self.ws.numel(), _stream(self.device)),
+                   "srt3d_reconstruct")
         return out
 
     def state(self):

@@ -39,6 +39,29 @@ int check_state(const srt3d_state* st) {
     return SRT3D_OK;
 }
 
+// Scratch of srt3d_reconstruct_noalloc (the initialisation's workspace), one copy per device.
+// Host code never uses the array's name as an address: each device's copy is looked up once with
+// hipGetSymbolAddress, with that device current, and kept in scratch_addr.
+static __device__ __align__(256) unsigned char scratch[SRT3D_STATIC_SCRATCH_BYTES];
+std::atomic<void*> scratch_addr[kMaxDevices];
+
+// Device address of the current device's scratch (write-once cache: concurrent first calls on a
+// device store the same address).
+hipError_t device_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    void* ptr = scratch_addr[dev].load(std::memory_order_acquire);
+    if (ptr == nullptr) {
+        if ((e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+        if (ptr == nullptr) return hipErrorInvalidSymbol;
+        scratch_addr[dev].store(ptr, std::memory_order_release);
+    }
+    *out = ptr;
+    return hipSuccess;
+}
+
 }  // namespace
 
 namespace srt3d {
@@ -320,6 +343,22 @@ int srt3d_reconstruct(const float* d_z, const int32_t* d_n, const double* d_irf,
     return srt3d_finalize(st, d_n, p, d_depth, d_intensity, d_active, d_bg, stream);
 }
 
+int srt3d_reconstruct_noalloc(const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len,
+                              int32_t irf_origin, const srt3d_params* p, srt3d_state* st, float* d_depth,
+                              float* d_intensity, uint8_t* d_active, float* d_bg, void* stream) {
+    // host-side checks first: a problem too large for the static scratch is refused before any
+    // HIP call
+    int rc = check_params(p);
+    if (rc != SRT3D_OK) return rc;
+    if (init_ws_bytes(*p) > (size_t)SRT3D_STATIC_SCRATCH_BYTES) return SRT3D_ESCRATCH;
+    if ((rc = check_state(st)) != SRT3D_OK) return rc;
+    if (!d_z || !d_n || !d_irf || irf_len < 1 || irf_origin < 0 || irf_origin >= irf_len) return SRT3D_EINVAL;
+    void* ws = nullptr;
+    if (device_scratch(&ws) != hipSuccess) return SRT3D_EDEVICE;
+    return srt3d_reconstruct(d_z, d_n, d_irf, irf_len, irf_origin, p, st, d_depth, d_intensity, d_active, d_bg, ws,
+                             (size_t)SRT3D_STATIC_SCRATCH_BYTES, stream);
+}
+
 int srt3d_phase_indices(const int32_t* d_x, int64_t N, int32_t T, int32_t m, int32_t* d_k, void* stream) {
     if (N < 0 || !sketch_dims_ok(T, m) || (N > 0 && (!d_x || !d_k))) return SRT3D_EINVAL;
     return dev_status(launch_phase_indices(d_x, N, T, m, d_k, as_stream(stream)));
@@ -336,6 +375,7 @@ const char* srt3d_strerror(int status) {
         case SRT3D_EINVAL: return "invalid argument";
         case SRT3D_ENOMEM: return "workspace too small";
         case SRT3D_EDEVICE: return "HIP device error";
+        case SRT3D_ESCRATCH: return "problem needs more scratch than the static array of srt3d_reconstruct_noalloc";
         default: return "unknown status";
     }
 }

@@ -41,6 +41,26 @@ def test_version_and_strerror(lib):
     assert lib.srt3d_strerror(-2) == b"workspace too small"
 
 
+def test_noalloc_reconstruct_rejects_too_large_problems_on_the_host(lib):
+    """srt3d_reconstruct_noalloc refuses a problem whose scratch exceeds its static array before
+    any HIP call (the pointers below are never dereferenced), and names the reason."""
+    assert lib.srt3d_strerror(L.SRT3D_ESCRATCH).startswith(b"problem needs more scratch")
+    p = L._Params()
+    lib.srt3d_params_default(ctypes.byref(p), 16, 16, 8192, 64, 1)
+    assert lib.srt3d_init_workspace_bytes(ctypes.byref(p)) <= L.STATIC_SCRATCH_BYTES
+    p.init_stride = 1                               # 8192 grid points: 4.2 MB of grid table
+    assert lib.srt3d_init_workspace_bytes(ctypes.byref(p)) > L.STATIC_SCRATCH_BYTES
+    st = L._State()
+    fake = 0x1000
+    for b in range(2):
+        st.t[b] = st.alpha[b] = st.active[b] = fake
+    st.hhat = st.scal = fake
+    args = [ctypes.c_void_p(fake)] * 3 + [17, 8, ctypes.byref(p), ctypes.byref(st)] + [ctypes.c_void_p(0)] * 4
+    assert lib.srt3d_reconstruct_noalloc(*args, None) == L.SRT3D_ESCRATCH
+    p.K_max = 4                                     # invalid parameters are still EINVAL
+    assert lib.srt3d_reconstruct_noalloc(*args, None) == L.SRT3D_EINVAL
+
+
 def test_params_default(lib):
     p = srt.Params.default(256, 256, 4096, 16)
     assert (p.iters, p.R, p.Rb, p.init_stride) == (50, 2, 1, 0)
@@ -48,9 +68,13 @@ def test_params_default(lib):
 
 
 def test_workspace_queries(lib):
-    assert lib.srt3d_hist_workspace_bytes(1024, 16, 0) == 32 * 1024 * 4
-    assert lib.srt3d_hist_workspace_bytes(1024, 16, 1) == 2 * 32 * 1024 * 2
-    assert lib.srt3d_hist_workspace_bytes(1024, 16, 2) == 3 * 32 * 1024 * 2
+    # split F planes (16-row column tiles x T), then G: FP64 [chunks of 32 bins, rounded up to a
+    # multiple of 4][column tiles x 16], each part rounded up to 256 bytes
+    G = 32 * 32 * 8
+    assert lib.srt3d_hist_workspace_bytes(1024, 16, 0) == 32 * 1024 * 4 + G
+    assert lib.srt3d_hist_workspace_bytes(1024, 16, 1) == 2 * 32 * 1024 * 2 + G
+    assert lib.srt3d_hist_workspace_bytes(1024, 16, 2) == 3 * 32 * 1024 * 2 + G
+    assert lib.srt3d_hist_workspace_bytes(96, 1, 0) == 16 * 96 * 4 + 4 * 16 * 8   # 3 chunks -> 4
     assert lib.srt3d_hist_workspace_bytes(1024, 33, 0) == 0
     assert lib.srt3d_hist_workspace_bytes(1024, 16, 3) == 0
     assert lib.srt3d_hist_workspace_bytes(16384, 4, 0) == 0
