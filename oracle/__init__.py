@@ -18,6 +18,9 @@ Modules
           steps, several starts, the lowest loss kept): the comparison system.
   weighted  eq. (6) with W = Sigma^{-1}: the sketch covariance from the characteristic
           function and a two-step weighted fit of each pixel.
+  rt3d_full  full-data RT3D: SRT3D's iteration with the data step on the Poisson likelihood of
+          each pixel's whole histogram (eq. 1), the quality reference the sketched
+          reconstruction is compared with on tiny frames.
 
 Parity status: every function is pinned by the `-m "not gpu"` tests in
 `tests/test_oracle_*.py` against closed forms, invariants or brute force.
