@@ -44,6 +44,8 @@ def parse():
                     help="sketch path timed in the step (both meet the same oracle tolerance)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=96, help="serving workload: number of requests")
+    ap.add_argument("--serving-requests", type=int, default=96,
+                    help="requests of the short serving leg in the default line (0 = skip)")
     ap.add_argument("--budget-gib", type=float, default=4.0, help="serving workload: HBM budget")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
@@ -84,6 +86,69 @@ def sketch_valu(method: str, workload: str):
     if not m_sha or not m_v or m_sha.group(1) != sha:
         return None
     return float(m_v.group(1))
+
+
+def _oracle_sketch_chunk(args):
+    """Worker of the all-cores CPU baseline: the oracle's sketch of one contiguous block of
+    pixels (a spawned process: it imports numpy and the oracle only)."""
+    stamps, offsets, T, m = args
+    from threadpoolctl import threadpool_limits
+
+    from oracle import sketch as OS
+    with threadpool_limits(limits=1):
+        return OS.sketch(stamps, offsets, T, m)
+
+
+def cpu_cores() -> int:
+    """Host cores the baseline may use: the process's CPU set, at most 16 (one GPU's share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline_all_cores(frame, w, params):
+    """The oracle on the whole frame with every host core: the FP64 sketch of all pixels split
+    into contiguous blocks over a process pool, then the FP64 SRT3D oracle (init, all iterations,
+    background, output) in this process on the pool-computed sketch, numpy's thread pools
+    limited to the same core count.  Wall time of both, no extrapolation."""
+    import multiprocessing as mp
+
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import srt3d as O
+
+    spec = frame.spec
+    cores = cpu_cores()
+    st_np, off_np = frame.stamps.cpu().numpy(), frame.offsets.cpu().numpy()
+    bounds = np.linspace(0, spec.P, 4 * cores + 1).astype(np.int64)
+    chunks = []
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        lo, hi = off_np[a], off_np[b]
+        chunks.append((st_np[lo:hi], off_np[a:b + 1] - lo, spec.T, w.m))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_sketch_chunk, chunks[:cores])          # start-up and imports, untimed
+        t0 = time.perf_counter()
+        parts = pool.map(_oracle_sketch_chunk, chunks)
+        t_sketch = time.perf_counter() - t0
+    zc = np.concatenate([p[0] for p in parts])
+    nn = np.concatenate([p[1] for p in parts]).astype(np.int64)
+    op = O.Params(spec.T, w.m, w.K_max, iters=params.iters, r_min=params.r_min)
+    with threadpool_limits(limits=cores):
+        t0 = time.perf_counter()
+        O.reconstruct(zc, nn, frame.irf, frame.irf_origin, spec.rows, spec.cols, op)
+        t_srt3d = time.perf_counter() - t0
+    per_frame = t_sketch + t_srt3d
+    return {
+        "value": 1.0 / per_frame, "unit": "frames/s", "cores": cores, "kind": "oracle",
+        "sample": (f"FP64 numpy oracle on the whole frame: sketch of all {spec.P} pixels over a pool of "
+                   f"{cores} processes ({t_sketch:.2f} s), then init + {params.iters} iterations + background "
+                   f"+ output in one process with numpy's thread pools limited to {cores} ({t_srt3d:.2f} s)"),
+        "photons_per_s": float(frame.stamps.numel()) / t_sketch,
+    }
 
 
 def cpu_baseline(frame, z_gpu, n_gpu, w, params):
@@ -189,11 +254,11 @@ def precision_report(args):
           flush=True)
 
 
-def serving_report(args):
-    """Continuous batching of a Poisson stream of frames (32^2..512^2, 10..2000 photons/px,
-    T = 2048, m = 8..32, sketch + 20 iterations each).  The single-slot sequential capacity is
-    measured first; the stream is then replayed at 0.5x and 0.9x that rate on 4 slots under an
-    HBM budget.  Latency = completion - arrival."""
+def serving_measure(count: int, budget_bytes: int, seed: int = 4):
+    """Continuous batching of a Poisson stream of `count` frames (32^2..512^2, 10..2000
+    photons/px, T = 2048, m = 8..32, sketch + 20 iterations each).  The single-slot sequential
+    capacity is measured first; the stream is then replayed at 0.5x and 0.9x that rate on 4
+    slots under an HBM budget.  Latency = completion - arrival (host clock)."""
     import numpy as np
     import torch
 
@@ -202,7 +267,7 @@ def serving_report(args):
     from paper_2203_00952_amd.serve import Request, percentile, serve
 
     dev = torch.device("cuda:0")
-    stream = synth.request_stream(seed=4, count=args.requests, rate_hz=1.0, iters=20)
+    stream = synth.request_stream(seed=seed, count=count, rate_hz=1.0, iters=20)
     reqs, photons = [], 0
     for q in stream:
         f = synth.make_frame(q.frame, device=dev)
@@ -210,25 +275,32 @@ def serving_report(args):
         reqs.append(Request(q.rid, f.stamps, f.offsets, torch.from_numpy(f.irf).to(dev), f.irf_origin, params))
         photons += int(f.stamps.numel())
     torch.cuda.synchronize()
-    budget = int(args.budget_gib * (1 << 30))
-    serve(reqs[:4], slots=1, budget_bytes=budget)                       # warm-up
+    serve(reqs[:4], slots=1, budget_bytes=budget_bytes)                 # warm-up
     for r in reqs:
         r.arrival = 0.0
-    recs, _, _ = serve(reqs, slots=1, budget_bytes=budget)
+    recs, _, _ = serve(reqs, slots=1, budget_bytes=budget_bytes)
     capacity = len(reqs) / max(r.finished for r in recs)
     res = {"workload": "serving", "requests": len(reqs), "photons": photons, "slots": 4,
-           "hbm_budget_bytes": budget, "single_slot_capacity_frames_per_s": capacity}
+           "sizes": sorted({q.frame.rows for q in stream}), "hbm_budget_bytes": budget_bytes,
+           "single_slot_capacity_frames_per_s": capacity}
     for load in (0.5, 0.9):
         rate = load * capacity
         for r, q in zip(reqs, stream):
             r.arrival = q.arrival_s / rate
-        recs, _, peak = serve(reqs, slots=4, budget_bytes=budget)
+        recs, _, peak = serve(reqs, slots=4, budget_bytes=budget_bytes)
         lat = [1e3 * r.latency for r in recs]
         makespan = max(r.finished for r in recs)
         res[f"load_{load}"] = {"arrival_rate_per_s": rate, "p50_ms": percentile(lat, 50),
                                "p99_ms": percentile(lat, 99), "mean_ms": float(np.mean(lat)),
                                "frames_per_s": len(reqs) / makespan, "peak_admitted_bytes": peak}
-    print(json.dumps(res), flush=True)
+    del reqs
+    torch.cuda.empty_cache()
+    return res
+
+
+def serving_report(args):
+    """The serving workload alone (`--requests` frames), one JSON line."""
+    print(json.dumps(serving_measure(args.requests, int(args.budget_gib * (1 << 30)))), flush=True)
 
 
 def table1_report(args):
@@ -512,8 +584,13 @@ def main():
             "achieved": valu / (sk_ms.mean() * 1e-3), "peak": VALU_PEAK, "unit": "wave instructions/s",
             "frac": valu / (sk_ms.mean() * 1e-3) / VALU_PEAK},
     }
+    # the serving workload's request stream, short (outside the timed steps): p50/p99 latency
+    # under Poisson arrivals at 0.5x and 0.9x of the measured single-slot capacity
+    if args.serving_requests > 0:
+        res["serving"] = serving_measure(args.serving_requests, int(args.budget_gib * (1 << 30)))
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(frame, z, n, w, params)
+        res["cpu_baseline"] = cpu_baseline_all_cores(frame, w, params)
+        res["cpu_baseline"]["single_core"] = cpu_baseline(frame, z, n, w, params)
     print(json.dumps(res), flush=True)
 
 

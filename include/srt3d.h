@@ -113,6 +113,35 @@ typedef struct srt3d_state {
 void srt3d_params_default(srt3d_params* p, int32_t rows, int32_t cols, int32_t T, int32_t m,
                           int32_t K_max);
 
+/* Calls whose workspace size srt3d_workspace_bytes reports. */
+enum srt3d_call {
+    SRT3D_CALL_SKETCH = 0,         /* srt3d_sketch, srt3d_sketch_binned: no workspace (0 bytes) */
+    SRT3D_CALL_RECONSTRUCT = 1,    /* srt3d_init, srt3d_reconstruct, srt3d_smle */
+    SRT3D_CALL_SMLE_WEIGHTED = 2,  /* srt3d_smle_weighted, srt3d_weighted_fit */
+    SRT3D_CALL_HIST_FP32 = 3,      /* srt3d_hist_prepare / srt3d_sketch_from_hist, by precision */
+    SRT3D_CALL_HIST_FP16X2 = 4,
+    SRT3D_CALL_HIST_BF16X3 = 5
+};
+
+/* ---------------------------------------------------------------------------------------
+ * Sizes of the caller-owned device memory.
+ * srt3d_workspace_bytes: the workspace of call `which` (srt3d_call) for the frame of p (p->T,
+ *   p->m and, for the reconstruction calls, the whole of p) with P pixels.  P must equal
+ *   p->rows * p->cols for SRT3D_CALL_RECONSTRUCT and SRT3D_CALL_SMLE_WEIGHTED; the sketch and
+ *   histogram calls read only p->T and p->m.  Returns 0 for invalid arguments (also for
+ *   SRT3D_CALL_SKETCH, which needs none).  The event-stream sketch's workspace depends on the
+ *   number of events: srt3d_sketch_events_workspace_bytes.
+ * srt3d_state_bytes: one device allocation that holds every array of srt3d_state for p (with
+ *   P = p->rows * p->cols pixels), each array starting on a 256-byte boundary; 0 when invalid.
+ * srt3d_state_carve: points st's arrays into such an allocation d_base of `bytes` bytes
+ *   (256-byte aligned) and sets st->cur = 0.  Host arithmetic only: nothing is enqueued.
+ *   Layout, in order: t[0], t[1], alpha[0], alpha[1] (float32 [P * K_max] each), active[0],
+ *   active[1] (uint8 [P * K_max] each), hhat (float32 [m][2]), scal (float32 [SRT3D_NSCAL]).
+ * ------------------------------------------------------------------------------------- */
+size_t srt3d_workspace_bytes(const srt3d_params* p, int32_t P, int32_t which);
+size_t srt3d_state_bytes(const srt3d_params* p, int32_t P);
+int srt3d_state_carve(srt3d_state* st, const srt3d_params* p, void* d_base, size_t bytes);
+
 /* ---------------------------------------------------------------------------------------
  * Phase table -- the frequencies of Section 2, w_l = 2 pi l / T, evaluated at integer phases:
  *     d_table[k] = (cos, sin)(2 pi k / T), k = 0..T-1, FP64 values rounded to FP32.

@@ -19,6 +19,7 @@ SRT3D_OK, SRT3D_EINVAL, SRT3D_ENOMEM, SRT3D_EDEVICE, SRT3D_ESCRATCH = 0, -1, -2,
 STATIC_SCRATCH_BYTES = 1 << 20
 PRECISIONS = {"fp32": 0, "fp16x2": 1, "bf16x3": 2}
 STAGES = {"data": 0, "depth": 1, "intensity": 2, "birth": 3}
+CALLS = {"sketch": 0, "reconstruct": 1, "smle_weighted": 2, "hist_fp32": 3, "hist_fp16x2": 4, "hist_bf16x3": 5}
 MAX_M_RECON, MAX_K, MAX_R, NSCAL, MAX_STARTS = 64, 3, 3, 8, 64
 
 
@@ -69,6 +70,9 @@ _SIGS = {
     "srt3d_finalize": (_I32, [ctypes.POINTER(_State), _VP, ctypes.POINTER(_Params), _VP, _VP, _VP, _VP, _VP]),
     "srt3d_reconstruct": (_I32, [_VP, _VP, _VP, _I32, _I32, ctypes.POINTER(_Params), ctypes.POINTER(_State),
                                  _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "srt3d_workspace_bytes": (_SZ, [ctypes.POINTER(_Params), _I32, _I32]),
+    "srt3d_state_bytes": (_SZ, [ctypes.POINTER(_Params), _I32]),
+    "srt3d_state_carve": (_I32, [ctypes.POINTER(_State), ctypes.POINTER(_Params), _VP, _SZ]),
     "srt3d_reconstruct_noalloc": (_I32, [_VP, _VP, _VP, _I32, _I32, ctypes.POINTER(_Params), ctypes.POINTER(_State),
                                          _VP, _VP, _VP, _VP, _VP]),
     "srt3d_phase_indices": (_I32, [_VP, _I64, _I32, _I32, _VP, _VP]),
@@ -357,24 +361,29 @@ class Reconstructor:
         self.p = params
         self.device = torch.device(device)
         PK = params.P * params.K_max
-        self.t = torch.zeros((2, PK), dtype=torch.float32, device=self.device)
-        self.alpha = torch.zeros((2, PK), dtype=torch.float32, device=self.device)
-        self.active = torch.zeros((2, PK), dtype=torch.uint8, device=self.device)
-        self.hhat = torch.zeros((params.m, 2), dtype=torch.float32, device=self.device)
-        self.scal = torch.zeros(NSCAL, dtype=torch.float32, device=self.device)
         self._cp = params.c()
-        ws = _lib().srt3d_init_workspace_bytes(ctypes.byref(self._cp))
-        if ws == 0:
+        ws = _lib().srt3d_workspace_bytes(ctypes.byref(self._cp), params.P, CALLS["reconstruct"])
+        nstate = _lib().srt3d_state_bytes(ctypes.byref(self._cp), params.P)
+        if ws == 0 or nstate == 0:
             raise ValueError(f"invalid reconstruction parameters {params}")
         self.ws = _workspace(ws, self.device)
+        # every state array in one allocation, laid out by srt3d_state_carve
+        self._state_buf = _workspace(nstate, self.device)
+        self._state_buf.zero_()
         self._st = _State()
-        for b in range(2):
-            self._st.t[b] = self.t[b].data_ptr()
-            self._st.alpha[b] = self.alpha[b].data_ptr()
-            self._st.active[b] = self.active[b].data_ptr()
-        self._st.hhat = self.hhat.data_ptr()
-        self._st.scal = self.scal.data_ptr()
-        self._st.cur = 0
+        _check(_lib().srt3d_state_carve(ctypes.byref(self._st), ctypes.byref(self._cp), _ptr(self._state_buf),
+                                        nstate), "srt3d_state_carve")
+        base = self._state_buf.data_ptr()
+
+        def view(addr, n, dtype):
+            off = addr - base
+            return self._state_buf[off:off + n * torch.empty((), dtype=dtype).element_size()].view(dtype)
+
+        self.t = [view(self._st.t[b], PK, torch.float32) for b in range(2)]
+        self.alpha = [view(self._st.alpha[b], PK, torch.float32) for b in range(2)]
+        self.active = [view(self._st.active[b], PK, torch.uint8) for b in range(2)]
+        self.hhat = view(self._st.hhat, 2 * params.m, torch.float32).view(params.m, 2)
+        self.scal = view(self._st.scal, NSCAL, torch.float32)
 
     @property
     def cur(self) -> int:

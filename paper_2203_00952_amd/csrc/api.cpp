@@ -110,6 +110,67 @@ void srt3d_params_default(srt3d_params* p, int32_t rows, int32_t cols, int32_t T
     p->birth_every = 0;
 }
 
+namespace {
+inline size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+// the state's arrays in carving order, with their sizes
+void state_parts(const srt3d_params& p, size_t (&bytes)[8]) {
+    const size_t PK = (size_t)p.rows * p.cols * p.K_max;
+    for (int b = 0; b < 4; ++b) bytes[b] = up256(PK * sizeof(float));     // t[0], t[1], alpha[0], alpha[1]
+    for (int b = 4; b < 6; ++b) bytes[b] = up256(PK);                      // active[0], active[1]
+    bytes[6] = up256((size_t)p.m * 2 * sizeof(float));                    // hhat
+    bytes[7] = up256((size_t)SRT3D_NSCAL * sizeof(float));                // scal
+}
+}  // namespace
+
+size_t srt3d_workspace_bytes(const srt3d_params* p, int32_t P, int32_t which) {
+    if (!p || P < 1) return 0;
+    switch (which) {
+        case SRT3D_CALL_RECONSTRUCT:
+            if (check_params(p) != SRT3D_OK || (int64_t)p->rows * p->cols != P) return 0;
+            return init_ws_bytes(*p);
+        case SRT3D_CALL_SMLE_WEIGHTED:
+            if ((int64_t)p->rows * p->cols != P) return 0;
+            return srt3d_smle_weighted_workspace_bytes(p);
+        case SRT3D_CALL_HIST_FP32:
+        case SRT3D_CALL_HIST_FP16X2:
+        case SRT3D_CALL_HIST_BF16X3:
+            return srt3d_hist_workspace_bytes(p->T, p->m, which - SRT3D_CALL_HIST_FP32);
+        default: return 0;   // SRT3D_CALL_SKETCH needs none; anything else is invalid
+    }
+}
+
+size_t srt3d_state_bytes(const srt3d_params* p, int32_t P) {
+    if (check_params(p) != SRT3D_OK || (int64_t)p->rows * p->cols != P) return 0;
+    size_t parts[8], total = 0;
+    state_parts(*p, parts);
+    for (size_t b : parts) total += b;
+    return total;
+}
+
+int srt3d_state_carve(srt3d_state* st, const srt3d_params* p, void* d_base, size_t bytes) {
+    if (!st || check_params(p) != SRT3D_OK || !d_base || !aligned(d_base, 256)) return SRT3D_EINVAL;
+    size_t parts[8], total = 0;
+    state_parts(*p, parts);
+    for (size_t b : parts) total += b;
+    if (bytes < total) return SRT3D_ENOMEM;
+    char* c = static_cast<char*>(d_base);
+    void* ptr[8];
+    for (int i = 0; i < 8; ++i) {
+        ptr[i] = c;
+        c += parts[i];
+    }
+    st->t[0] = static_cast<float*>(ptr[0]);
+    st->t[1] = static_cast<float*>(ptr[1]);
+    st->alpha[0] = static_cast<float*>(ptr[2]);
+    st->alpha[1] = static_cast<float*>(ptr[3]);
+    st->active[0] = static_cast<uint8_t*>(ptr[4]);
+    st->active[1] = static_cast<uint8_t*>(ptr[5]);
+    st->hhat = static_cast<float*>(ptr[6]);
+    st->scal = static_cast<float*>(ptr[7]);
+    st->cur = 0;
+    return SRT3D_OK;
+}
+
 int srt3d_sketch(const int32_t* d_stamps, int64_t N, const int64_t* d_offsets, int32_t P, int32_t T, int32_t m,
                  const float* d_table, float* d_z, int32_t* d_n, double* d_acc, int64_t* d_nacc, int32_t* d_err,
                  void* stream) {

@@ -1450,6 +1450,21 @@ __device__ __forceinline__ void id_update(const float* rt, const bool* was_on, f
     project_capped_simplex<K>(an, keep);
 }
 
+// Tile of this workgroup, XCD-aware: workgroups go to the eight XCDs in turn (linear id mod 8), and
+// each XCD has its own L2.  XCD x takes a contiguous band of the row-major tile order, so a tile's
+// ring of neighbouring pixels (written by the previous launch) mostly comes from tiles that ran on
+// the same XCD.  A bijection of the linear ids for any tile count.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int2 xcd_tile() {
+    const int nx = gridDim.x, total = gridDim.x * gridDim.y;
+    const int id = blockIdx.x + nx * blockIdx.y;
+    const int per = (total + kXcds - 1) / kXcds, rem = total % kXcds;
+    const int x = id % kXcds, k = id / kXcds;
+    const int start = rem == 0 ? x * per : x * (per - 1) + (x < rem ? x : rem);
+    const int t = start + k;
+    return make_int2(t % nx, t / nx);
+}
+
 // Load an (EY x E cells) x K region with origin (gi0, gj0) into LDS (row stride E cells); cells
 // outside the frame are inactive with depth 0.  With WITH_R the intensity n * alpha is loaded too.
 template <int K, bool WITH_R>
@@ -1482,7 +1497,8 @@ __global__ __launch_bounds__(kTile * kTile) void depth_denoise_kernel(
     constexpr int E = kTile + 2 * R;
     __shared__ float s_t[E * E * K];
     __shared__ uint8_t s_a[E * E * K];
-    const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
+    const int2 tile = xcd_tile();
+    const int i0 = tile.y * kTile, j0 = tile.x * kTile;
     load_region<K, false>(s_t, s_a, nullptr, E, E, i0 - R, j0 - R, A, t_in, a_in, act_in, nullptr);
     __syncthreads();
     const int ti = threadIdx.x / kTile, tj = threadIdx.x % kTile;
@@ -1508,7 +1524,8 @@ __global__ __launch_bounds__(kTile * kTile) void intensity_denoise_kernel(
     constexpr int E = kTile + 2 * R;
     __shared__ float s_t[E * E * K], s_r[E * E * K];
     __shared__ uint8_t s_a[E * E * K];
-    const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
+    const int2 tile = xcd_tile();
+    const int i0 = tile.y * kTile, j0 = tile.x * kTile;
     load_region<K, true>(s_t, s_a, s_r, E, E, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
     __syncthreads();
     const int ti = threadIdx.x / kTile, tj = threadIdx.x % kTile;
@@ -1546,6 +1563,7 @@ __global__ __launch_bounds__(kTile * kTile) void intensity_denoise_kernel(
 // iteration and the ring makes each tile fit 1.9 times its own pixels; the separate launch fits
 // each pixel once.  dd_point sees the same inputs either way, so both forms give the same bits.
 constexpr int kIterTY = 8, kIterTX = 16;
+
 constexpr int kIterPix = kIterTY * kIterTX;
 constexpr int kIterThreads = kIterPix * kLanesPerPixel;
 
@@ -1565,7 +1583,8 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
     __shared__ uint8_t s_a1[E1Y * E1 * K];
     __shared__ float2 s_h[SRT3D_MAX_M_RECON];
     __shared__ float s_ddp[(K == 1 && !DD_DONE && E1Y * E1 <= kIterThreads / 2) ? E1Y * E1 * kDDPart : 1];
-    const int i0 = blockIdx.y * kIterTY, j0 = blockIdx.x * kIterTX;
+    const int2 tile = xcd_tile();
+    const int i0 = tile.y * kIterTY, j0 = tile.x * kIterTX;
     // The data step's sketch slice (this thread's pixel and harmonics) is loaded first, into
     // registers, and stays in flight through the denoisers: the barriers below order LDS only.
     const int sub = threadIdx.x % kLanesPerPixel, pl = threadIdx.x / kLanesPerPixel;   // pl < kIterPix

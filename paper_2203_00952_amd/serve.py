@@ -14,9 +14,15 @@ does not depend on what runs beside it.
 
 The scheduler itself (`Scheduler`) knows nothing about GPUs: it drives an executor through
 `start / done / finish_time`, which lets the admission logic be tested with a simulated one.
+When nothing can be admitted it does not spin: an executor with `token / wait` (the GPU one)
+blocks it until a running job completes or the next request arrives; otherwise `idle(dt)` is
+called.
 """
 from __future__ import annotations
 
+import ctypes
+import queue
+import threading
 import time
 from dataclasses import dataclass, field
 from typing import Any, Callable
@@ -49,7 +55,7 @@ class Scheduler:
     slots: int
     budget_bytes: int
     clock: Callable[[], float] = time.perf_counter
-    idle: Callable[[float], None] = lambda dt: None      # called when nothing can progress
+    idle: Callable[[float], None] | None = None    # called when nothing can progress (no `wait`)
     peak_bytes: int = field(default=0, init=False)
 
     def run(self, jobs: list[Job]) -> list[Record]:
@@ -62,7 +68,9 @@ class Scheduler:
         running: dict[int, tuple[Job, Any, float]] = {}
         in_use = 0
         out: list[Record] = []
+        waits = self.idle is None and hasattr(self.executor, "wait")
         while pending or running:
+            token = self.executor.token() if waits else None
             now = self.clock() - t0
             for slot in list(running):
                 job, handle, admitted = running[slot]
@@ -82,8 +90,14 @@ class Scheduler:
                 running[slot] = (job, self.executor.start(job, slot), admitted)
                 progressed = True
             if not progressed and (pending or running):
-                nxt = pending[0].arrival - now if pending and not running else 0.0
-                self.idle(max(nxt, 0.0))
+                if waits:
+                    # sleep until a running job completes (the token moves) or the next arrival
+                    nxt = pending[0].arrival - (self.clock() - t0) if pending and pending[0].arrival > now else None
+                    if running or nxt is not None:
+                        self.executor.wait(token, None if nxt is None else max(nxt, 0.0))
+                elif self.idle is not None:
+                    nxt = pending[0].arrival - now if pending and not running else 0.0
+                    self.idle(max(nxt, 0.0))
         return sorted(out, key=lambda r: r.rid)
 
 
@@ -123,8 +137,19 @@ class Request:
         return Job(self.rid, self.arrival, self.working_bytes(), self)
 
 
+class _Running:
+    """A started request: its completion event, the buffers that must outlive it, and the host
+    time at which a watcher saw it complete (None until then)."""
+
+    def __init__(self, event, keep):
+        self.event, self.keep = event, keep
+        self.finished = None
+
+
 class GpuExecutor:
-    """Runs each admitted request on its slot's stream: sketch, then reconstruct."""
+    """Runs each admitted request on its slot's stream: sketch, then reconstruct.  One watcher
+    thread per slot blocks on the slot's completion events (blocking-sync events, so the thread
+    sleeps in the driver) and wakes the scheduler through a condition variable."""
 
     def __init__(self, slots: int, device="cuda:0"):
         import torch
@@ -135,6 +160,29 @@ class GpuExecutor:
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
         self.results: dict[int, dict] = {}
+        self._event_sync = L._lib().hipEventSynchronize
+        self._event_sync.restype = ctypes.c_int
+        self._event_sync.argtypes = [ctypes.c_void_p]
+        self._cv = threading.Condition()
+        self._completions = 0
+        self._queues = [queue.SimpleQueue() for _ in range(slots)]
+        self._watchers = [threading.Thread(target=self._watch, args=(q,), daemon=True) for q in self._queues]
+        for t in self._watchers:
+            t.start()
+
+    def _watch(self, q):
+        while True:
+            h = q.get()
+            if h is None:
+                return
+            # hipEventSynchronize through ctypes, which releases the interpreter lock while the
+            # thread sleeps (the symbol resolves through libsrt3d's own HIP runtime dependency,
+            # the runtime that created the event)
+            self._event_sync(h.event._as_parameter_)
+            with self._cv:
+                h.finished = time.perf_counter()
+                self._completions += 1
+                self._cv.notify_all()
 
     def start(self, job: Job, slot: int):
         torch, L = self.torch, self.L
@@ -145,22 +193,44 @@ class GpuExecutor:
             z, n = L.sketch(req.stamps, req.offsets, req.params.T, req.params.m, table=table, method=req.sketch)
             rec = L.Reconstructor(req.params, self.device)
             out = rec.reconstruct(z, n, req.irf, req.irf_origin)
-            ev = torch.cuda.Event()
+            ev = torch.cuda.Event(blocking=True)
             ev.record(s)
         self.results[req.rid] = out
-        return (ev, rec, z, n)
+        h = _Running(ev, (rec, z, n))
+        self._queues[slot].put(h)
+        return h
 
     def done(self, handle) -> bool:
-        return handle[0].query()
+        with self._cv:
+            return handle.finished is not None
 
     def finish_time(self, handle, t0: float) -> float:
-        return time.perf_counter() - t0
+        return handle.finished - t0
+
+    def token(self) -> int:
+        with self._cv:
+            return self._completions
+
+    def wait(self, token: int, timeout):
+        """Block until a completion after `token` was observed, or `timeout` seconds (None: no
+        limit) have passed."""
+        with self._cv:
+            self._cv.wait_for(lambda: self._completions != token, timeout)
+
+    def close(self):
+        for q in self._queues:
+            q.put(None)
+        for t in self._watchers:
+            t.join()
 
 
 def serve(requests: list[Request], slots: int = 4, budget_bytes: int = 16 << 30, device="cuda:0"):
     """Serve `requests` (arrival times in seconds from now); returns (records, results by rid)."""
     ex = GpuExecutor(slots, device)
-    sch = Scheduler(ex, slots, budget_bytes)
-    recs = sch.run([r.job() for r in requests])
-    ex.torch.cuda.synchronize()
+    try:
+        sch = Scheduler(ex, slots, budget_bytes)
+        recs = sch.run([r.job() for r in requests])
+        ex.torch.cuda.synchronize()
+    finally:
+        ex.close()
     return recs, ex.results, sch.peak_bytes

@@ -61,6 +61,42 @@ def test_noalloc_reconstruct_rejects_too_large_problems_on_the_host(lib):
     assert lib.srt3d_reconstruct_noalloc(*args, None) == L.SRT3D_EINVAL
 
 
+def test_workspace_and_state_size_queries(lib):
+    """srt3d_workspace_bytes agrees with the per-call queries; srt3d_state_bytes and
+    srt3d_state_carve lay the state out as the header states (host arithmetic only)."""
+    p = L._Params()
+    lib.srt3d_params_default(ctypes.byref(p), 256, 256, 4096, 16, 1)
+    P = 256 * 256
+    ws = lambda which, PP=P: lib.srt3d_workspace_bytes(ctypes.byref(p), PP, which)   # noqa: E731
+    assert ws(L.CALLS["reconstruct"]) == lib.srt3d_init_workspace_bytes(ctypes.byref(p)) > 0
+    assert ws(L.CALLS["smle_weighted"]) == lib.srt3d_smle_weighted_workspace_bytes(ctypes.byref(p)) > 0
+    for i, prec in enumerate(("hist_fp32", "hist_fp16x2", "hist_bf16x3")):
+        assert ws(L.CALLS[prec]) == lib.srt3d_hist_workspace_bytes(4096, 16, i) > 0
+    assert ws(L.CALLS["sketch"]) == 0
+    assert ws(L.CALLS["reconstruct"], P + 1) == 0           # P must match rows * cols
+    assert ws(99) == 0
+    up = lambda b: (b + 255) // 256 * 256                   # noqa: E731
+    for K in (1, 2, 3):
+        p.K_max = K
+        PK = P * K
+        expect = 4 * up(4 * PK) + 2 * up(PK) + up(8 * 16) + up(4 * L.NSCAL)
+        n = lib.srt3d_state_bytes(ctypes.byref(p), P)
+        assert n == expect
+        st = L._State()
+        base = 0x7f0000000000
+        assert lib.srt3d_state_carve(ctypes.byref(st), ctypes.byref(p), ctypes.c_void_p(base), n) == L.SRT3D_OK
+        offs = [st.t[0], st.t[1], st.alpha[0], st.alpha[1], st.active[0], st.active[1], st.hhat, st.scal]
+        assert [o - base for o in offs] == [0, up(4 * PK), 2 * up(4 * PK), 3 * up(4 * PK), 4 * up(4 * PK),
+                                            4 * up(4 * PK) + up(PK), 4 * up(4 * PK) + 2 * up(PK),
+                                            4 * up(4 * PK) + 2 * up(PK) + up(128)]
+        assert st.cur == 0
+        assert lib.srt3d_state_carve(ctypes.byref(st), ctypes.byref(p), ctypes.c_void_p(base), n - 1) == L.SRT3D_ENOMEM
+        assert lib.srt3d_state_carve(ctypes.byref(st), ctypes.byref(p), ctypes.c_void_p(base + 16), n) == L.SRT3D_EINVAL
+    assert lib.srt3d_state_bytes(ctypes.byref(p), P - 1) == 0
+    p.K_max = 4
+    assert lib.srt3d_state_bytes(ctypes.byref(p), P) == 0
+
+
 def test_params_default(lib):
     p = srt.Params.default(256, 256, 4096, 16)
     assert (p.iters, p.R, p.Rb, p.init_stride) == (50, 2, 1, 0)

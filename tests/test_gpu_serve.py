@@ -11,8 +11,9 @@ from tests.gpu_common import device
 
 pytestmark = pytest.mark.gpu
 
-MIX = [(32, 500.0, 8), (64, 1500.0, 16), (48, 200.0, 12), (128, 300.0, 20), (32, 2000.0, 32), (96, 800.0, 10),
-       (16, 50.0, 4), (80, 1000.0, 24)]
+# (side, photons/px, m): the serving workload's sizes 32^2..512^2 among smaller and odd ones
+MIX = [(32, 500.0, 8), (256, 400.0, 16), (48, 200.0, 12), (128, 300.0, 20), (512, 60.0, 32), (96, 800.0, 10),
+       (16, 50.0, 4), (80, 1000.0, 24), (256, 1500.0, 8)]
 
 
 def _requests(dev, arrivals):

@@ -1,5 +1,7 @@
 """The serving scheduler with a simulated executor and clock (no GPU): admission by arrival,
 free slots and the memory budget; first-come first-served; every request finishes."""
+import time
+
 import numpy as np
 import pytest
 
@@ -92,3 +94,60 @@ def test_oversized_request_is_rejected():
 def test_percentile():
     assert percentile([1, 2, 3, 4], 50) == 2.5
     assert percentile([5], 99) == 5
+
+
+class ThreadExecutor:
+    """Jobs complete on timer threads after `duration(job)` seconds of wall time; the executor
+    offers token/wait like the GPU one, and counts how often the scheduler polls `done`."""
+
+    def __init__(self, duration):
+        import threading
+
+        self.duration = duration
+        self.cv = threading.Condition()
+        self.completions = 0
+        self.polls = 0
+        self.ends = {}
+
+    def start(self, job, slot):
+        import threading
+
+        def fin():
+            with self.cv:
+                self.ends[job.rid] = time.perf_counter()
+                self.completions += 1
+                self.cv.notify_all()
+
+        threading.Timer(self.duration(job), fin).start()
+        return job.rid
+
+    def done(self, h):
+        with self.cv:
+            self.polls += 1
+            return h in self.ends
+
+    def finish_time(self, h, t0):
+        return self.ends[h] - t0
+
+    def token(self):
+        with self.cv:
+            return self.completions
+
+    def wait(self, token, timeout):
+        with self.cv:
+            self.cv.wait_for(lambda: self.completions != token, timeout)
+
+
+def test_scheduler_sleeps_instead_of_spinning():
+    """With an executor that can block, the scheduler waits for completions and arrivals: the
+    number of `done` polls stays near (jobs x slots), not proportional to wall time."""
+    jobs = [Job(i, 0.004 * i, 100) for i in range(20)]
+    ex = ThreadExecutor(lambda j: 0.01)
+    sch = Scheduler(ex, slots=2, budget_bytes=1000)
+    t0 = time.perf_counter()
+    recs = sch.run(jobs)
+    wall = time.perf_counter() - t0
+    assert [r.rid for r in recs] == list(range(20))
+    assert all(r.finished >= r.admitted >= r.arrival - 1e-3 for r in recs)
+    assert wall > 0.08                       # 20 jobs of 10 ms on 2 slots
+    assert ex.polls < 400, ex.polls          # a spinning loop polls ~1e5 times in 0.1 s
