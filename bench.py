@@ -544,6 +544,35 @@ def main():
                  "weighted_fit_steps": wsteps if weighted else 0,
                  "weighted_fit_ms": e_p[1].elapsed_time(e_p[2]) if weighted else None}
     del pw
+    # SRT3D with W_p = Sigma(theta_0)^-1 inside the data step (eq. 8 with a per-pixel W): init,
+    # the weights, the iterations and finalize, on the step's sketch (outside the timed steps)
+    weighted_srt3d = None
+    if weighted:
+        wr = srt.Reconstructor(params, dev)
+
+        def wrun(ev=None):
+            if ev:
+                ev[0].record(stream)
+            wr.init(z, n, irf, frame.irf_origin)
+            wr.weighted_prepare(n, irf, frame.irf_origin)
+            if ev:
+                ev[1].record(stream)
+            wr.weighted_iterate(z, n, params.iters)
+            if ev:
+                ev[2].record(stream)
+            wr.finalize(n)
+            if ev:
+                ev[3].record(stream)
+
+        wrun()
+        e_w = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        wrun(e_w)
+        torch.cuda.synchronize()
+        weighted_srt3d = {"iters": params.iters, "weights_bytes": int(wr.wws.numel()),
+                          "init_and_weights_ms": e_w[0].elapsed_time(e_w[1]),
+                          "iterations_ms": e_w[1].elapsed_time(e_w[2]),
+                          "total_ms": e_w[0].elapsed_time(e_w[3])}
+        del wr
     res = {
         "metric": METRIC,
         "value": args.steps / wall,
@@ -568,6 +597,7 @@ def main():
                                 "hbm_frac": ev_alg / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                 "algorithmic_bytes": ev_alg, "same_as_step_sketch": ev_same},
         "pixelwise_estimators": pixelwise,
+        "weighted_srt3d": weighted_srt3d,
         "sketch_ms": {"mean": float(sk_ms.mean()), "p50": float(np.percentile(sk_ms, 50)),
                       "p99": float(np.percentile(sk_ms, 99))},
         "srt3d_ms": {"mean": float(rc_ms.mean()), "p50": float(np.percentile(rc_ms, 50)),

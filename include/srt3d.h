@@ -120,7 +120,8 @@ enum srt3d_call {
     SRT3D_CALL_SMLE_WEIGHTED = 2,  /* srt3d_smle_weighted, srt3d_weighted_fit */
     SRT3D_CALL_HIST_FP32 = 3,      /* srt3d_hist_prepare / srt3d_sketch_from_hist, by precision */
     SRT3D_CALL_HIST_FP16X2 = 4,
-    SRT3D_CALL_HIST_BF16X3 = 5
+    SRT3D_CALL_HIST_BF16X3 = 5,
+    SRT3D_CALL_WEIGHTED_ITERATE = 6 /* srt3d_weighted_prepare, _step, _iterate */
 };
 
 /* ---------------------------------------------------------------------------------------
@@ -357,6 +358,33 @@ int srt3d_weighted_fit(srt3d_state* st, const float* d_z, const int32_t* d_n, co
 int srt3d_smle_weighted(const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len,
                         int32_t irf_origin, const srt3d_params* p, int32_t starts, int32_t witers,
                         srt3d_state* st, float* d_loss, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * SRT3D with the precision weighting inside its data step -- eq. (8) with a per-pixel W
+ * (Section 2 allows any positive definite W in eq. (6) and names W = Sigma^{-1}, eq. (5), the
+ * efficient one; Section 3's SRT3D uses W = I).  W_p = Sigma(theta_0)^{-1} is the inverse of the
+ * ridged covariance of the sketch's 2m real coordinates (as in srt3d_smle_weighted) at the
+ * pixel's points theta_0, held fixed.  The data step is SRT3D's with the loss n e^T W e,
+ * e = [Re(Phi - z), Im(Phi - z)]: t <- t - gamma_t 2 n (J^T W e)_t, then alpha at the new t, then
+ * the projection; gamma are the W = I steps of srt3d_init with the frame's n_max replaced by
+ * n_w = max_p n_p max_i sum_j |W_p,ij| (a bound of the largest eigenvalue of n_p W_p, equal to
+ * c n_max when every W_p = c I, so that case is exactly SRT3D).  The denoisers are SRT3D's.
+ * srt3d_weighted_prepare: W_p from the current half of st (normally right after srt3d_init,
+ *   whose hhat and scal it needs) and n_w, into d_ws (srt3d_workspace_bytes(p, P,
+ *   SRT3D_CALL_WEIGHTED_ITERATE) bytes, 256-byte aligned: 4 (2m)^2 bytes per pixel); the impulse
+ *   response as for srt3d_init.
+ * srt3d_weighted_step: one weighted data step, in place (st->cur unchanged).
+ * srt3d_weighted_iterate: `iters` x (weighted data step, depth denoiser, intensity denoiser);
+ *   st->cur is unchanged after each iteration.
+ * Constraints: as srt3d_init, and m <= SRT3D_MAX_M_WEIGHTED, 2 m < T.
+ * ------------------------------------------------------------------------------------- */
+int srt3d_weighted_prepare(srt3d_state* st, const int32_t* d_n, const double* d_irf, int32_t irf_len,
+                           int32_t irf_origin, const srt3d_params* p, void* d_ws, size_t ws_bytes,
+                           void* stream);
+int srt3d_weighted_step(srt3d_state* st, const float* d_z, const int32_t* d_n, const srt3d_params* p,
+                        const void* d_ws, size_t ws_bytes, void* stream);
+int srt3d_weighted_iterate(srt3d_state* st, const float* d_z, const int32_t* d_n, const srt3d_params* p,
+                           int32_t iters, const void* d_ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------
  * Inspection entry points used to check the exact part of the sketch and every launch form.

@@ -19,7 +19,8 @@ SRT3D_OK, SRT3D_EINVAL, SRT3D_ENOMEM, SRT3D_EDEVICE, SRT3D_ESCRATCH = 0, -1, -2,
 STATIC_SCRATCH_BYTES = 1 << 20
 PRECISIONS = {"fp32": 0, "fp16x2": 1, "bf16x3": 2}
 STAGES = {"data": 0, "depth": 1, "intensity": 2, "birth": 3}
-CALLS = {"sketch": 0, "reconstruct": 1, "smle_weighted": 2, "hist_fp32": 3, "hist_fp16x2": 4, "hist_bf16x3": 5}
+CALLS = {"sketch": 0, "reconstruct": 1, "smle_weighted": 2, "hist_fp32": 3, "hist_fp16x2": 4, "hist_bf16x3": 5,
+         "weighted_iterate": 6}
 MAX_M_RECON, MAX_K, MAX_R, NSCAL, MAX_STARTS = 64, 3, 3, 8, 64
 
 
@@ -73,6 +74,11 @@ _SIGS = {
     "srt3d_workspace_bytes": (_SZ, [ctypes.POINTER(_Params), _I32, _I32]),
     "srt3d_state_bytes": (_SZ, [ctypes.POINTER(_Params), _I32]),
     "srt3d_state_carve": (_I32, [ctypes.POINTER(_State), ctypes.POINTER(_Params), _VP, _SZ]),
+    "srt3d_weighted_prepare": (_I32, [ctypes.POINTER(_State), _VP, _VP, _I32, _I32, ctypes.POINTER(_Params), _VP,
+                                      _SZ, _VP]),
+    "srt3d_weighted_step": (_I32, [ctypes.POINTER(_State), _VP, _VP, ctypes.POINTER(_Params), _VP, _SZ, _VP]),
+    "srt3d_weighted_iterate": (_I32, [ctypes.POINTER(_State), _VP, _VP, ctypes.POINTER(_Params), _I32, _VP, _SZ,
+                                      _VP]),
     "srt3d_reconstruct_noalloc": (_I32, [_VP, _VP, _VP, _I32, _I32, ctypes.POINTER(_Params), ctypes.POINTER(_State),
                                          _VP, _VP, _VP, _VP, _VP]),
     "srt3d_phase_indices": (_I32, [_VP, _I64, _I32, _I32, _VP, _VP]),
@@ -455,6 +461,42 @@ class Reconstructor:
                                          ctypes.byref(self._cp), witers, _ptr(loss), _ptr(self.ws), self.ws.numel(),
                                          _stream(self.device)), "srt3d_weighted_fit")
         return loss
+
+    def weighted_prepare(self, n, irf: torch.Tensor, origin: int):
+        """W_p = Sigma(theta_0)^{-1} at the current points and the frame bound
+        (srt3d_weighted_prepare), into this object's weighted workspace."""
+        self._zn(None, n)
+        _dev(irf, torch.float64, "irf")
+        need = _lib().srt3d_workspace_bytes(ctypes.byref(self._cp), self.p.P, CALLS["weighted_iterate"])
+        if need == 0:
+            raise ValueError("weighted SRT3D needs m <= 32 and 2 m < T")
+        if getattr(self, "wws", None) is None or self.wws.numel() < need:
+            self.wws = _workspace(need, self.device)
+        _check(_lib().srt3d_weighted_prepare(ctypes.byref(self._st), _ptr(n), _ptr(irf), irf.numel(), origin,
+                                             ctypes.byref(self._cp), _ptr(self.wws), self.wws.numel(),
+                                             _stream(self.device)), "srt3d_weighted_prepare")
+
+    def weighted_step(self, z, n):
+        """One weighted data step in place (srt3d_weighted_step); after weighted_prepare."""
+        self._zn(z, n)
+        _check(_lib().srt3d_weighted_step(ctypes.byref(self._st), _ptr(z), _ptr(n), ctypes.byref(self._cp),
+                                          _ptr(self.wws), self.wws.numel(), _stream(self.device)),
+               "srt3d_weighted_step")
+
+    def weighted_iterate(self, z, n, iters: int):
+        """`iters` weighted iterations (srt3d_weighted_iterate); after weighted_prepare."""
+        self._zn(z, n)
+        _check(_lib().srt3d_weighted_iterate(ctypes.byref(self._st), _ptr(z), _ptr(n), ctypes.byref(self._cp), iters,
+                                             _ptr(self.wws), self.wws.numel(), _stream(self.device)),
+               "srt3d_weighted_iterate")
+
+    def weighted_matrices(self):
+        """W_p from the weighted workspace as [P, 2m, 2m] (a view), and the frame bound n_w."""
+        P, d = self.p.P, 2 * self.p.m
+        off = 256 + (d * 8 + 255) // 256 * 256
+        W = self.wws[off:off + P * d * d * 4].view(torch.float32).view(P, d, d)
+        nw = self.wws[:4].view(torch.float32)
+        return W, nw
 
     def step(self, stage: str, z, n):
         self._zn(z, n)

@@ -135,6 +135,10 @@ size_t srt3d_workspace_bytes(const srt3d_params* p, int32_t P, int32_t which) {
         case SRT3D_CALL_HIST_FP16X2:
         case SRT3D_CALL_HIST_BF16X3:
             return srt3d_hist_workspace_bytes(p->T, p->m, which - SRT3D_CALL_HIST_FP32);
+        case SRT3D_CALL_WEIGHTED_ITERATE:
+            if (check_params(p) != SRT3D_OK || (int64_t)p->rows * p->cols != P) return 0;
+            if (p->m > SRT3D_MAX_M_WEIGHTED || 2 * p->m >= p->T) return 0;
+            return wsrt_ws_bytes(*p);
         default: return 0;   // SRT3D_CALL_SKETCH needs none; anything else is invalid
     }
 }
@@ -381,6 +385,49 @@ int srt3d_iterate(srt3d_state* st, const float* d_z, const int32_t* d_n, const s
             if (launch_birth(*p, d_z, d_n, *st, st->cur, s) != hipSuccess) return SRT3D_EDEVICE;
             if (launch_data_step(*p, d_z, d_n, *st, st->cur, s) != hipSuccess) return SRT3D_EDEVICE;
         }
+    }
+    return SRT3D_OK;
+}
+
+namespace {
+int check_weighted(const srt3d_params* p, const srt3d_state* st, const void* d_ws, size_t ws_bytes) {
+    int rc = check_params(p);
+    if (rc != SRT3D_OK) return rc;
+    if ((rc = check_state(st)) != SRT3D_OK) return rc;
+    if (p->m > SRT3D_MAX_M_WEIGHTED || 2 * p->m >= p->T) return SRT3D_EINVAL;
+    if (!d_ws || !aligned(d_ws, 256) || !aligned(st->hhat, 8)) return SRT3D_EINVAL;
+    if (ws_bytes < wsrt_ws_bytes(*p)) return SRT3D_ENOMEM;
+    return SRT3D_OK;
+}
+}  // namespace
+
+int srt3d_weighted_prepare(srt3d_state* st, const int32_t* d_n, const double* d_irf, int32_t irf_len,
+                           int32_t irf_origin, const srt3d_params* p, void* d_ws, size_t ws_bytes, void* stream) {
+    const int rc = check_weighted(p, st, d_ws, ws_bytes);
+    if (rc != SRT3D_OK) return rc;
+    if (!d_n || !d_irf || irf_len < 1 || irf_origin < 0 || irf_origin >= irf_len) return SRT3D_EINVAL;
+    return dev_status(launch_wsrt_prepare(*p, d_irf, irf_len, irf_origin, d_n, *st, st->cur, d_ws, as_stream(stream)));
+}
+
+int srt3d_weighted_step(srt3d_state* st, const float* d_z, const int32_t* d_n, const srt3d_params* p,
+                        const void* d_ws, size_t ws_bytes, void* stream) {
+    const int rc = check_weighted(p, st, d_ws, ws_bytes);
+    if (rc != SRT3D_OK) return rc;
+    if (!d_z || !d_n || !aligned(d_z, 8)) return SRT3D_EINVAL;
+    return dev_status(launch_wsrt_data_step(*p, d_z, d_n, *st, st->cur, d_ws, as_stream(stream)));
+}
+
+int srt3d_weighted_iterate(srt3d_state* st, const float* d_z, const int32_t* d_n, const srt3d_params* p,
+                           int32_t iters, const void* d_ws, size_t ws_bytes, void* stream) {
+    const int rc = check_weighted(p, st, d_ws, ws_bytes);
+    if (rc != SRT3D_OK) return rc;
+    if (!d_z || !d_n || !aligned(d_z, 8) || iters < 0) return SRT3D_EINVAL;
+    hipStream_t s = as_stream(stream);
+    const int c = st->cur;
+    for (int it = 0; it < iters; ++it) {
+        if (launch_wsrt_data_step(*p, d_z, d_n, *st, c, d_ws, s) != hipSuccess) return SRT3D_EDEVICE;
+        if (launch_depth_denoise(*p, *st, c, 1 - c, s) != hipSuccess) return SRT3D_EDEVICE;
+        if (launch_intensity_denoise(*p, d_n, *st, 1 - c, c, s) != hipSuccess) return SRT3D_EDEVICE;
     }
     return SRT3D_OK;
 }

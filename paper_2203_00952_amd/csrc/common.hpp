@@ -113,5 +113,12 @@ hipError_t launch_iteration(const srt3d_params& p, const float* z, const int32_t
 hipError_t launch_finalize(const srt3d_params& p, const int32_t* n, const srt3d_state& st, float* depth,
                            float* intensity, uint8_t* active, float* bg, hipStream_t s);
 size_t init_ws_bytes(const srt3d_params& p);
+// SRT3D with W_p = Sigma(theta_0)^{-1} in the data step: workspace size, preparation (W_p and the
+// frame bound from the current state of half `half`), one weighted data step in place
+size_t wsrt_ws_bytes(const srt3d_params& p);
+hipError_t launch_wsrt_prepare(const srt3d_params& p, const double* irf, int irf_len, int irf_origin,
+                               const int32_t* n, const srt3d_state& st, int half, void* ws, hipStream_t s);
+hipError_t launch_wsrt_data_step(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st,
+                                 int half, const void* ws, hipStream_t s);
 
 }  // namespace srt3d

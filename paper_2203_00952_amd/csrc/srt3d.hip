@@ -1022,31 +1022,16 @@ struct Whitener {
     }
 };
 
+// Sigma(theta) of the pixel of this segment, ridged, and its Cholesky factor: lane i builds row i
+// of Sigma from Psi_0..Psi_2m (eq. 4 at the sums and differences of the frequencies), then the
+// row-oriented factorisation leaves L_ij (j <= i) in wh.row[j] and 1 / L_jj in wh.invd[j].  Rows and
+// columns 2m..M2-1 are identity.  psi: the segment's 2m + 1 LDS slots.  Every thread of the block
+// must call it (one workgroup barrier).
 template <int K, int M2>
-__global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, const float* __restrict__ z,
-                                                    const int32_t* __restrict__ n, const float2* __restrict__ h2,
-                                                    float* __restrict__ t_io, float* __restrict__ a_io,
-                                                    const uint8_t* __restrict__ act, float* __restrict__ loss_out) {
-    constexpr int kWaves = 256 / 64;
-    constexpr int kPPW = 64 / M2;                      // pixels per wave, one per segment
-    __shared__ float2 s_psi[kWaves][kPPW][2 * M2 + 1];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int seg = lane / M2, i = lane % M2, base = seg * M2;
-    const int pix_raw = (blockIdx.x * kWaves + wv) * kPPW + seg;
-    const bool valid = pix_raw < A.P;
-    const int pix = valid ? pix_raw : A.P - 1;
-    const int m = A.m, T = A.T;
-    const float Tf = (float)T, invT = 1.0f / Tf, twoinvT = 2.0f / Tf;
-    float tk[K], ak[K];
-    bool on[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int64_t q = (int64_t)pix * K + k;
-        tk[k] = t_io[q];
-        ak[k] = a_io[q];
-        on[k] = act[q] != 0;
-    }
-    // characteristic function Psi_j, j = 0..2m, at theta_1
+__device__ __forceinline__ void w_factor(const float2* __restrict__ h2, int i, int base, int m, int T, const float* tk,
+                                         const float* ak, const bool* on, float2* psi, Whitener<M2>& wh) {
+    const float invT = 1.0f / (float)T, twoinvT = 2.0f / (float)T;
+    // characteristic function Psi_j, j = 0..2m, at theta
     for (int j = i; j <= 2 * m; j += M2) {
         float2 v = make_float2(j == 0 ? 1.f : 0.f, 0.f);
         if (j > 0) {
@@ -1059,15 +1044,14 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
                 v.y += ak[k] * g.y;
             }
         }
-        s_psi[wv][seg][j] = v;
+        psi[j] = v;
     }
     __syncthreads();
     // row i of Sigma
-    Whitener<M2> wh;
     float (&row)[M2] = wh.row;
     float (&invd)[M2] = wh.invd;
     {
-        const float2* ps = s_psi[wv][seg];
+        const float2* ps = psi;
         const bool ri = i < m;
         const int a = (ri ? i : i - m) + 1;
         const float2 pa = i < 2 * m ? ps[a] : make_float2(0.f, 0.f);
@@ -1113,11 +1097,39 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
 #pragma unroll
         for (int c = j + 1; c < M2; ++c) row[c] -= lj * sbcast<M2>(lj, base, c);
     }
+}
+
+template <int K, int M2>
+__global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, const float* __restrict__ z,
+                                                    const int32_t* __restrict__ n, const float2* __restrict__ h2,
+                                                    float* __restrict__ t_io, float* __restrict__ a_io,
+                                                    const uint8_t* __restrict__ act, float* __restrict__ loss_out) {
+    constexpr int kWaves = 256 / 64;
+    constexpr int kPPW = 64 / M2;                      // pixels per wave, one per segment
+    __shared__ float2 s_psi[kWaves][kPPW][2 * M2 + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int seg = lane / M2, i = lane % M2, base = seg * M2;
+    const int pix_raw = (blockIdx.x * kWaves + wv) * kPPW + seg;
+    const bool valid = pix_raw < A.P;
+    const int pix = valid ? pix_raw : A.P - 1;
+    const int m = A.m, T = A.T;
+    const float Tf = (float)T, invT = 1.0f / Tf, twoinvT = 2.0f / Tf;
+    float tk[K], ak[K];
+    bool on[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t q = (int64_t)pix * K + k;
+        tk[k] = t_io[q];
+        ak[k] = a_io[q];
+        on[k] = act[q] != 0;
+    }
+    Whitener<M2> wh;
+    w_factor<K, M2>(h2, i, base, m, T, tk, ak, on, s_psi[wv][seg], wh);
     if constexpr (Whitener<M2>::kInverse) {
         // lane i: row i of L^{-1}, the forward substitution of the unit vectors
 #pragma unroll
         for (int v = 0; v < M2; ++v) wh.linv[v] = i == v ? 1.f : 0.f;
-        w_forward<M2, M2>(row, invd, wh.linv, i, base);
+        w_forward<M2, M2>(wh.row, wh.invd, wh.linv, i, base);
     }
     const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m);
     const float nq = (float)n[pix];
@@ -1209,6 +1221,135 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
     }
     loss_out[pix] = loss;
 }
+
+// ----------------------------------------------------------------------------- weighted SRT3D
+// Eq. (8) with a per-pixel W inside SRT3D's data step: W_p = Sigma(theta_0)^{-1}, the inverse of
+// the ridged covariance of the sketch's 2m real coordinates at the pixel's points theta_0 (the
+// state when prepared, normally the initialisation), held fixed.  The data step is SRT3D's with
+// the loss n e^T W e, e = [Re(Phi - z), Im(Phi - z)]: gradient 2 n J^T W e, steps the W = I ones
+// with n_max replaced by n_w = max_p n_p max_i sum_j |W_p,ij| (a Gershgorin bound of the largest
+// eigenvalue of W_p, exact for W_p = c I).
+//
+// wprep_kernel: one segment of M2 >= 2m lanes per pixel; Sigma and its Cholesky factor as in the
+// weighted pixelwise fit, the rows of L^{-1} by forward substitution of the unit vectors, then
+// W_ij = sum_k (L^{-1})_ki (L^{-1})_kj through LDS; lane i writes row i of W_p ([P][2m][2m], FP32)
+// and the frame's n_w is an atomic maximum of the (non-negative) float bits.
+template <int K, int M2>
+__global__ __launch_bounds__(256) void wprep_kernel(IterArgs A, const int32_t* __restrict__ n,
+                                                    const float2* __restrict__ h2, const float* __restrict__ t_in,
+                                                    const float* __restrict__ a_in, const uint8_t* __restrict__ act,
+                                                    float* __restrict__ W, unsigned int* __restrict__ nw_bits) {
+    constexpr int kWaves = 256 / 64;
+    constexpr int kPPW = 64 / M2;
+    __shared__ float2 s_psi[kWaves][kPPW][2 * M2 + 1];
+    __shared__ float s_li[kWaves][kPPW][M2][M2 + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int seg = lane / M2, i = lane % M2, base = seg * M2;
+    const int pix_raw = (blockIdx.x * kWaves + wv) * kPPW + seg;
+    const bool valid = pix_raw < A.P;
+    const int pix = valid ? pix_raw : A.P - 1;
+    const int m = A.m, twom = 2 * A.m;
+    float tk[K], ak[K];
+    bool on[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t q = (int64_t)pix * K + k;
+        tk[k] = t_in[q];
+        ak[k] = a_in[q];
+        on[k] = act[q] != 0;
+    }
+    Whitener<M2> wh;
+    w_factor<K, M2>(h2, i, base, m, A.T, tk, ak, on, s_psi[wv][seg], wh);
+    float li[M2];
+#pragma unroll
+    for (int v = 0; v < M2; ++v) li[v] = i == v ? 1.f : 0.f;
+    w_forward<M2, M2>(wh.row, wh.invd, li, i, base);
+    float (*sl)[M2 + 1] = s_li[wv][seg];
+#pragma unroll
+    for (int c = 0; c < M2; ++c) sl[i][c] = li[c];
+    __syncthreads();
+    float gsum = 0.f;
+    if (i < twom) {
+        float* wrow = W + ((int64_t)pix * twom + i) * twom;
+        for (int j = 0; j < twom; ++j) {
+            float acc = 0.f;
+            for (int k = i > j ? i : j; k < twom; ++k) acc = fmaf(sl[k][i], sl[k][j], acc);
+            if (valid) wrow[j] = acc;
+            gsum += fabsf(acc);
+        }
+    }
+#pragma unroll
+    for (int o = M2 / 2; o > 0; o >>= 1) gsum = fmaxf(gsum, __shfl_xor(gsum, o, 64));
+    if (valid && i == 0) atomicMax(nw_bits, __float_as_uint(gsum * (float)n[pix]));
+}
+
+// One weighted data step of every pixel, in place on the current half: lane i < 2m of the pixel's
+// segment holds row i of W_p; v = W e through one broadcast and one FMA per column.
+template <int K, int M2>
+__global__ __launch_bounds__(256) void wdata_kernel(IterArgs A, const float* __restrict__ z,
+                                                    const int32_t* __restrict__ n, const float2* __restrict__ hhat,
+                                                    const float* __restrict__ scal, const float* __restrict__ W,
+                                                    const unsigned int* __restrict__ nw_bits, float* __restrict__ t_io,
+                                                    float* __restrict__ a_io, const uint8_t* __restrict__ act) {
+    constexpr int kWaves = 256 / 64;
+    constexpr int kPPW = 64 / M2;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int seg = lane / M2, i = lane % M2, base = seg * M2;
+    const int pix_raw = (blockIdx.x * kWaves + wv) * kPPW + seg;
+    const bool valid = pix_raw < A.P;
+    const int pix = valid ? pix_raw : A.P - 1;
+    const int m = A.m, twom = 2 * A.m, T = A.T;
+    const float Tf = (float)T;
+    float tk[K], ak[K];
+    bool on[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t q = (int64_t)pix * K + k;
+        tk[k] = t_io[q];
+        ak[k] = a_io[q];
+        on[k] = act[q] != 0;
+    }
+    float wrow[M2];
+    const float* wp = W + ((int64_t)pix * twom + (i < twom ? i : 0)) * twom;
+#pragma unroll
+    for (int c = 0; c < M2; ++c) wrow[c] = (i < twom && c < twom) ? wp[c] : 0.f;
+    // the W = I steps with n_max replaced by n_w
+    const float nw = __uint_as_float(*nw_bits);
+    const float gam_t = nw > 0.f ? scal[1] * (scal[0] / nw) : 0.f;
+    const float gam_a = nw > 0.f ? scal[2] * (scal[0] / nw) : 0.f;
+    const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m);
+    const float nq = (float)n[pix];
+    // g = 2 n J^T W e at (tt, ak)
+    auto grad = [&](const float* tt, float* g) {
+        float r, jc[2 * K];
+        w_residual<K>(zp, hhat, i, m, T, tt, ak, on, r, jc);          // r = z - Phi
+        const float e = -r;
+        float v = 0.f;
+#pragma unroll
+        for (int c = 0; c < M2; ++c) v = fmaf(wrow[c], sbcast<M2>(e, base, c), v);
+#pragma unroll
+        for (int c = 0; c < 2 * K; ++c) g[c] = 2.f * nq * seg_sum<M2>(jc[c] * v);
+    };
+    float g[2 * K];
+    grad(tk, g);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (on[k]) tk[k] = wrap_t(tk[k] - gam_t * g[k], Tf);
+    grad(tk, g);
+    float an[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) an[k] = on[k] ? ak[k] - gam_a * g[K + k] : ak[k];
+    project_capped_simplex<K>(an, on);
+    if (!valid || i != 0) return;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t q = (int64_t)pix * K + k;
+        t_io[q] = tk[k];
+        a_io[q] = an[k];
+    }
+}
+
+__global__ void fill_u32_kernel(unsigned int* __restrict__ p, unsigned int v) { *p = v; }
 
 // ----------------------------------------------------------------------------- denoisers
 // Solve the leading D x D block of M x = b by M = L diag(d) L^T (unit lower L), with
@@ -1928,6 +2069,55 @@ hipError_t launch_wsmle(const srt3d_params& p, const double* irf, int irf_len, i
     else if (2 * p.m <= 32) { SRT3D_WSMLE(32); }
     else { SRT3D_WSMLE(64); }
 #undef SRT3D_WSMLE
+    return hipGetLastError();
+}
+
+// weighted-SRT3D workspace: n_w (256 bytes), the spectrum to harmonic 2m, then W [P][2m][2m]
+static size_t wsrt_spec_offset() { return 256; }
+static size_t wsrt_w_offset(const srt3d_params& p) {
+    return wsrt_spec_offset() + (((size_t)2 * p.m * sizeof(float2) + 255) & ~(size_t)255);
+}
+size_t wsrt_ws_bytes(const srt3d_params& p) {
+    return wsrt_w_offset(p) + (size_t)p.rows * p.cols * (2 * p.m) * (2 * p.m) * sizeof(float);
+}
+
+hipError_t launch_wsrt_prepare(const srt3d_params& p, const double* irf, int irf_len, int irf_origin,
+                               const int32_t* n, const srt3d_state& st, int half, void* ws, hipStream_t s) {
+    const IterArgs A = make_args(p);
+    char* w = static_cast<char*>(ws);
+    unsigned int* nw = reinterpret_cast<unsigned int*>(w);
+    float2* h2 = reinterpret_cast<float2*>(w + wsrt_spec_offset());
+    float* Wm = reinterpret_cast<float*>(w + wsrt_w_offset(p));
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(1), 0, s, nw, 0u);
+    hipLaunchKernelGGL(spectrum_kernel, dim3(1), dim3(1024), 0, s, irf, irf_len, irf_origin, p.T, 2 * p.m, h2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+#define SRT3D_WPREP(M2_)                                                                                            \
+    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((wprep_kernel<KK, M2_>), dim3((unsigned)((A.P + 4 * (64 / M2_) - 1) /    \
+                                           (4 * (64 / M2_)))), dim3(256), 0, s, A, n, h2, st.t[half],             \
+                                           st.alpha[half], st.active[half], Wm, nw))
+    if (2 * p.m <= 16) { SRT3D_WPREP(16); }
+    else if (2 * p.m <= 32) { SRT3D_WPREP(32); }
+    else { SRT3D_WPREP(64); }
+#undef SRT3D_WPREP
+    return hipGetLastError();
+}
+
+hipError_t launch_wsrt_data_step(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st,
+                                 int half, const void* ws, hipStream_t s) {
+    const IterArgs A = make_args(p);
+    const char* w = static_cast<const char*>(ws);
+    const unsigned int* nw = reinterpret_cast<const unsigned int*>(w);
+    const float* Wm = reinterpret_cast<const float*>(w + wsrt_w_offset(p));
+    const float2* hh = reinterpret_cast<const float2*>(st.hhat);
+#define SRT3D_WDATA(M2_)                                                                                            \
+    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((wdata_kernel<KK, M2_>), dim3((unsigned)((A.P + 4 * (64 / M2_) - 1) /    \
+                                           (4 * (64 / M2_)))), dim3(256), 0, s, A, z, n, hh, st.scal, Wm, nw,     \
+                                           st.t[half], st.alpha[half], st.active[half]))
+    if (2 * p.m <= 16) { SRT3D_WDATA(16); }
+    else if (2 * p.m <= 32) { SRT3D_WDATA(32); }
+    else { SRT3D_WDATA(64); }
+#undef SRT3D_WDATA
     return hipGetLastError();
 }
 
