@@ -27,9 +27,10 @@ FLAGS = [
 ]
 
 
-# Per-source additions: the binned sketch reads every MFMA result with VALU right away, so its
-# accumulators go in VGPRs rather than AGPRs (no v_accvgpr_read per element).
-EXTRA = {"binned.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# Per-source additions: the binned sketch reads every MFMA result with VALU right away, and the
+# histogram sketch keeps its accumulators live across a wave-uniform branch, so in both the
+# accumulators go in VGPRs rather than AGPRs (no v_accvgpr copies).
+EXTRA = {"binned.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"], "hist.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src: str) -> str:

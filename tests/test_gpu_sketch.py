@@ -182,6 +182,26 @@ def test_hist_sketch_matches_oracle(precision, m):
     assert not bad.any()
 
 
+@pytest.mark.parametrize("T,m", [(8192, 32), (8192, 24), (32, 5), (96, 3), (2080, 9)])
+def test_hist_sketch_shapes(T, m):
+    """Every precision at the longest histogram (T = 8192: the largest staged F chunks and level
+    table in LDS, 3 and 4 column tiles), a single 32-bin chunk, chunk counts that are not a
+    multiple of the FP64 product's K (96 and 2080 bins), and a pixel count that leaves the last
+    workgroup with idle waves."""
+    dev = device()
+    spec, f, H = _hist_frame(dev, rows=23, cols=29, lam=1500.0, seed=T + m, T=T)
+    Hn = synth.frames.hist_as_uint(H)
+    zr, nr = OS.sketch_hist(Hn, m)
+    for precision in ("fp32", "fp16x2", "bf16x3"):
+        _print_case(test="hist_shapes", T=T, m=m, precision=precision)
+        z, n = srt.sketch_from_hist(H, m, precision)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(n.cpu().numpy(), nr)
+        bad, err, tol = sketch_violations(to_complex(z), zr, nr)
+        print(precision, "max err/tol", float((err / tol).max()))
+        assert not bad.any()
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp16x2", "bf16x3"])
 def test_hist_hi_counts_path(precision):
     """Counts at and above 2^8 / 2^11 exercise the exact hi/lo split of the 16-bit forms, and
