@@ -18,7 +18,8 @@
 //  The split and the q products run only for chunks where some deviation in the wave's rows
 //  needs them; elsewhere (most chunks) the deviations are formed two at a time with packed
 //  16-bit integer adds and turned into FP16 or BF16 exactly by a few bit operations.
-//  Level part: v_mfma_f64_16x16x4_f64 over the chunk levels, which each wave keeps in LDS.
+//  Level part: v_mfma_f64_16x16x4_f64 over the chunk levels, which each wave keeps in LDS, one
+//  product per group of 4 chunks inside the chunk loop.
 // A operands come straight from HBM into registers (each lane loads 8 consecutive counts of one
 // row, 16 B, which is exactly its slice of a 16x32 A tile), two chunks ahead of their use.  Each
 // 32-bin chunk of F is staged in LDS once per workgroup and read there by its four waves (F is
@@ -43,8 +44,9 @@ template <> struct Prec<SRT3D_PREC_BF16X3> { static constexpr int splits = 3, sh
 
 constexpr int kChunk = 32;                 // bins per chunk (one k-step of the 16-bit products)
 constexpr int kWavesPerBlock = 4;
+constexpr int kThreads = 64 * kWavesPerBlock;
 constexpr int kMT = 1;                     // 16-row tiles per wave
-constexpr int kDepth = 2;                  // chunks of counts in flight ahead of the one contracted
+constexpr int kDepth = 2;                  // chunks of counts in flight ahead of the one contracted (1, 2 or 4)
 
 __host__ __device__ static inline int n_tiles(int m) { return (2 * m + 15) / 16; }
 // chunks per row rounded up to the K of the FP64 product (4)
@@ -147,7 +149,7 @@ template <int PREC, int NT> __host__ __device__ constexpr int f_chunk_bytes() {
 // Dynamic LDS: two staged chunks of F, then per wave the chunk levels lv[k][32 rows] (uint16),
 // k < n_chunks4(T).
 template <int PREC, int NT>
-__global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restrict__ H, int P, int T, int m,
+__global__ __launch_bounds__(kThreads) void hist_mfma_kernel(const uint16_t* __restrict__ H, int P, int T, int m,
                                                         const void* __restrict__ ws, float* __restrict__ z,
                                                         int32_t* __restrict__ nout) {
     constexpr int S = Prec<PREC>::splits;
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
     constexpr int FP = f_pitch<PREC>(), FCB = f_chunk_bytes<PREC, NT>();
     constexpr int ROW_U4 = kChunk * E / 16;                 // 16-byte pieces of a column's chunk
     constexpr int FU4 = S * NT * 16 * ROW_U4;               // of the whole chunk
-    constexpr int FPT = (FU4 + 255) / 256;                  // per thread
+    constexpr int FPT = (FU4 + kThreads - 1) / kThreads;    // per thread
     extern __shared__ __align__(16) uint8_t lds_dyn[];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
@@ -173,18 +175,18 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
     // padding chunks have level 0 (their G rows are zero too)
     for (int i = nk * MT * 16 + lane; i < nk4 * MT * 16; i += 64) lv[i] = 0;
 
-    // Staging of F: thread x moves the 16-byte pieces x, x + 256 and x + 512 of a chunk (clamped
+    // Staging of F: thread x moves the 16-byte pieces x, x + kThreads, ... of a chunk (clamped
     // to the chunk's last piece, which some threads then move more than once).  Named registers,
     // not an array: an array carried across the loop stays in private memory.
-    static_assert(FPT <= 3, "a staged chunk is at most 768 pieces of 16 bytes");
+    static_assert(FPT <= 3, "at most three 16-byte pieces of a staged chunk per thread");
     const uint8_t* Fb = reinterpret_cast<const uint8_t*>(ws);
     auto f_src = [&](int u) {
-        const int idx = min((int)threadIdx.x + u * 256, FU4 - 1);
+        const int idx = min((int)threadIdx.x + u * kThreads, FU4 - 1);
         const int part = idx % ROW_U4, rowi = idx / ROW_U4;            // rowi = (s NT + b) 16 + c
         return Fb + ((int64_t)(rowi / rowsF) * plane + (int64_t)(rowi % rowsF) * T) * E + part * 16;
     };
     auto f_dst = [&](int u) {
-        const int idx = min((int)threadIdx.x + u * 256, FU4 - 1);
+        const int idx = min((int)threadIdx.x + u * kThreads, FU4 - 1);
         return (idx / ROW_U4) * FP + (idx % ROW_U4) * 16;
     };
     const uint8_t* fs0 = f_src(0);
@@ -228,20 +230,41 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
         const int64_t row = r0 + a * 16 + li;
         hrow[a] = H + (row < P ? row : (int64_t)P - 1) * T + 8 * kg;
     }
+    static_assert(4 % kDepth == 0, "the ring's slots follow the chunk's place in its group of 4");
     uint4 qr[kDepth][MT];
 #pragma unroll
     for (int d = 0; d < kDepth; ++d)
 #pragma unroll
         for (int a = 0; a < MT; ++a)
             qr[d][a] = *reinterpret_cast<const uint4*>(hrow[a] + min(d, nk - 1) * kChunk);
+    // Level part L = C . G on the FP64 matrix cores, one product per group of 4 chunks (its K),
+    // run as the group's last chunk is done: A = levels (chunk g + kg), B = G (chunk g + kg,
+    // column li).  The FP64 product leaves result row 4 i + kg in register i (the FP32 products
+    // leave row 4 kg + i there), so A's row li carries the levels of row 4 (li & 3) + (li >> 2):
+    // then register i holds row 4 kg + i, as in the FP32 accumulators.  Each lane loads its G
+    // value of a group as the group starts.
+    const double* G = reinterpret_cast<const double*>(reinterpret_cast<const char*>(ws) +
+                                                      dft_bytes(T, m, PREC));
+    const int prow = 4 * (li & 3) + (li >> 2);
+    v4d lacc[MT][NT];
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) lacc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    double gcur[NT];
+
     SRT3D_F_FETCH(0)
     SRT3D_F_STORE(0)
     lds_barrier();
-    for (int kb = 0; kb < nk; kb += kDepth)
+    for (int kb = 0; kb < nk; kb += 4)
 #pragma unroll
-    for (int d = 0; d < kDepth; ++d) {
+    for (int d = 0; d < 4; ++d) {
         const int kc = kb + d;
         if (kc >= nk) break;
+        if (d == 0) {
+#pragma unroll
+            for (int b = 0; b < NT; ++b) gcur[b] = G[(size_t)(kb + kg) * rowsF + b * 16 + li];
+        }
         SRT3D_F_FETCH(min(kc + 1, nk - 1))               // in flight during the contraction
         const uint8_t* fb = fbuf + (kc & 1) * FCB;
         uint32_t w[MT][4];                       // 8 counts of the lane's row, two per word
@@ -249,10 +272,10 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
         bool anyhi = false;
 #pragma unroll
         for (int a = 0; a < MT; ++a) {
-            const uint4 q = qr[d][a];               // (a row past the last one: the last row again)
+            const uint4 q = qr[d % kDepth][a];      // (a row past the last one: the last row again)
             w[a][0] = q.x, w[a][1] = q.y, w[a][2] = q.z, w[a][3] = q.w;
             // slot d, consumed, now takes chunk kc + kDepth
-            qr[d][a] = *reinterpret_cast<const uint4*>(hrow[a] + min(kc + kDepth, nk - 1) * kChunk);
+            qr[d % kDepth][a] = *reinterpret_cast<const uint4*>(hrow[a] + min(kc + kDepth, nk - 1) * kChunk);
             uint32_t s8 = 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) s8 = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, w[a][j]), u16x2{1, 1}, s8, false);
@@ -367,6 +390,16 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
                 }
             }
         }
+        if (d == 3 || kc == nk - 1) {
+            // the group's levels, this wave's own LDS writes (padding chunks hold level 0)
+#pragma unroll
+            for (int a = 0; a < MT; ++a) {
+                const double ca = (double)lv[(kb + kg) * (MT * 16) + a * 16 + prow];
+#pragma unroll
+                for (int b = 0; b < NT; ++b)
+                    lacc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca, gcur[b], lacc[a][b], 0, 0, 0);
+            }
+        }
         SRT3D_F_STORE((kc + 1) & 1)                      // (the last chunk again after the last one)
         lds_barrier();                                          // staged chunk kc + 1 complete, kc free
     }
@@ -381,40 +414,9 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
     }
     if (r0 >= P) return;                                        // (no barrier follows)
 
-    // Level part L = C . G on the FP64 matrix cores: A = levels (chunk 4 g + kg), B = G (chunk
-    // 4 g + kg, column li).  The FP64 product leaves result row 4 i + kg in register i (the FP32
-    // products leave row 4 kg + i there), so A's row li carries the levels of row
-    // 4 (li & 3) + (li >> 2): then register i holds row 4 kg + i, as in the FP32 accumulators.
-    // (The levels were written by this wave before the barriers of the chunk loop.)
-    const double* G = reinterpret_cast<const double*>(reinterpret_cast<const char*>(ws) +
-                                                      dft_bytes(T, m, PREC));
     const int twom = 2 * m;
-    const int prow = 4 * (li & 3) + (li >> 2);
 #pragma unroll
     for (int b = 0; b < NT; ++b) {
-        v4d lacc[MT];
-#pragma unroll
-        for (int a = 0; a < MT; ++a) lacc[a] = v4d{0.0, 0.0, 0.0, 0.0};
-        // G in batches of 8 loads, issued before the products that use them
-        for (int g0 = 0; g0 < nk4; g0 += 32) {
-            double gb[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int g = min(g0 + 4 * u, nk4 - 4);
-                gb[u] = G[(size_t)(g + kg) * rowsF + b * 16 + li];
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int g = g0 + 4 * u;
-                if (g < nk4) {
-#pragma unroll
-                    for (int a = 0; a < MT; ++a) {
-                        const double ca = (double)lv[(g + kg) * (MT * 16) + a * 16 + prow];
-                        lacc[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca, gb[u], lacc[a], 0, 0, 0);
-                    }
-                }
-            }
-        }
 #pragma unroll
         for (int a = 0; a < MT; ++a) {
 #pragma unroll
@@ -425,7 +427,7 @@ __global__ __launch_bounds__(256) void hist_mfma_kernel(const uint16_t* __restri
                 const int col = b * 16 + li;
                 if (row < P && col < twom)
                     z[row * twom + col] =
-                        n > 0 ? (float)(((double)acc[a][b][i] + lacc[a][i]) / (double)n) : 0.f;
+                        n > 0 ? (float)(((double)acc[a][b][i] + lacc[a][b][i]) / (double)n) : 0.f;
             }
         }
     }
@@ -444,8 +446,8 @@ static size_t hist_lds_bytes(int T) {
 template <int PREC, int NT>
 static hipError_t launch_hist_nt(const uint16_t* H, int P, int T, int m, const void* ws, float* z, int32_t* n,
                                  hipStream_t s) {
-    // two 16-row tiles per wave: 2048 waves at 256^2, which keeps more loads in flight than four
-    // tiles and more matrix work per load than one
+    // one 16-row tile per wave: 4096 waves at 256^2, four per SIMD (two tiles per wave measured
+    // slower: fewer waves to hide the loads and the barriers behind)
     const int64_t waves = ((int64_t)P + kMT * 16 - 1) / (kMT * 16);
     const unsigned blocks = (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
     const size_t lds = hist_lds_bytes<PREC, NT>(T);
@@ -455,7 +457,7 @@ static hipError_t launch_hist_nt(const uint16_t* H, int P, int T, int m, const v
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((hist_mfma_kernel<PREC, NT>), dim3(blocks), dim3(64 * kWavesPerBlock), lds, s,
+    hipLaunchKernelGGL((hist_mfma_kernel<PREC, NT>), dim3(blocks), dim3(kThreads), lds, s,
                        H, P, T, m, ws, z, n);
     return hipGetLastError();
 }
