@@ -223,9 +223,16 @@ __device__ __forceinline__ void mfma_tiles(uint8_t* hist, const float2* s_wm, co
                                            int lane, int dc, float* sre, float* sim, uint32_t& bsum) {
     const _Float16 bh = (_Float16)(float)(-1024 - dc);
     const v2h bias = {bh, bh};
+    if (MT == MTT) {
+        // every tile (the usual case): one straight block, so that one tile's loads and
+        // conversions are scheduled among another's matrix products
 #pragma unroll
-    for (int mt = 0; mt < MTT; ++mt)
-        if (mt < MT) mfma_tile<Q>(hist, s_wm, V, mt, lane, bias, sre, sim, bsum);
+        for (int mt = 0; mt < MTT; ++mt) mfma_tile<Q>(hist, s_wm, V, mt, lane, bias, sre, sim, bsum);
+    } else {
+#pragma unroll
+        for (int mt = 0; mt < MTT; ++mt)
+            if (mt < MT) mfma_tile<Q>(hist, s_wm, V, mt, lane, bias, sre, sim, bsum);
+    }
 }
 
 __device__ __forceinline__ void zero_hist_wave(uint8_t* hist, int bytes, int lane) {
@@ -339,33 +346,43 @@ __global__ __launch_bounds__(kBinThreads) __attribute__((amdgpu_waves_per_eu(Q =
                 }
             }
         }
-        // sum over the four row groups g, fixed order ((g0 + g1) + (g2 + g3)) in every lane
+        // Sum over the four row groups g in the fixed order (g0 + g1) + (g2 + g3).  Swapping the
+        // odd 16-lane rows of the real sums with the even rows of the imaginary sums and adding
+        // leaves row 0 with re(g0 + g1), row 1 with im(g0 + g1), rows 2 and 3 with the same for
+        // g2 + g3; swapping 32-lane halves and adding then gives rows 0 and 2 the real total and
+        // rows 1 and 3 the imaginary one.  Lane (row, c) stores component row & 1 of harmonic
+        // 16 q + c + 1, q = row >> 1 (with one set of harmonics, rows 2 and 3 store nothing).
+        float v[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            sre[q] += __shfl_xor(sre[q], 16, kWave);
-            sim[q] += __shfl_xor(sim[q], 16, kWave);
-            sre[q] += __shfl_xor(sre[q], 32, kWave);
-            sim[q] += __shfl_xor(sim[q], 32, kWave);
+            const auto p16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(sre[q]), __float_as_uint(sim[q]), false,
+                                                              false);
+            const float u = __uint_as_float(p16[0]) + __uint_as_float(p16[1]);
+            const auto p32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(u), __float_as_uint(u), false, false);
+            v[q] = __uint_as_float(p32[0]) + __uint_as_float(p32[1]);
         }
-        if (lane < 16 * Q) {
-            const int c = lane & 15, q = lane >> 4, l = 16 * q + c + 1;
-            float s0 = sre[0], s1 = sim[0];
-#pragma unroll
-            for (int qq = 1; qq < Q; ++qq)
-                if (q == qq) {
-                    s0 = sre[qq];
-                    s1 = sim[qq];
-                }
+        const int c = lane & 15, comp = (lane >> 4) & 1, qs = lane >> 5;
+        if (qs < Q) {
+            const int l = 16 * qs + c + 1;
+            const float val = Q == 1 ? v[0] : (qs == 0 ? v[0] : v[Q - 1]);
             if (l <= m) {
-                const int64_t o = pix * m * 2 + 2 * (l - 1);
-                const double inv = count_total > 0 ? 1.0 / (double)count_total : 0.0;
+                const int64_t o = pix * m * 2 + 2 * (l - 1) + comp;
+                // 1 / n in FP64: the reciprocal estimate and two Newton steps (n >= 1 is an
+                // integer, so no special case arises)
+                double inv = 0.0;
+                if (count_total > 0) {
+                    const double nd = (double)count_total;
+                    double r = __builtin_amdgcn_rcp(nd);
+                    r = fma(r, fma(-nd, r, 1.0), r);
+                    r = fma(r, fma(-nd, r, 1.0), r);
+                    inv = r;
+                }
                 if (acc) {
-                    const double a0 = acc[o] + (double)s0, a1 = acc[o + 1] + (double)s1;
-                    acc[o] = a0;
-                    acc[o + 1] = a1;
-                    *reinterpret_cast<float2*>(z + o) = make_float2((float)(a0 * inv), (float)(a1 * inv));
+                    const double a = acc[o] + (double)val;
+                    acc[o] = a;
+                    z[o] = (float)(a * inv);
                 } else {
-                    *reinterpret_cast<float2*>(z + o) = make_float2((float)((double)s0 * inv), (float)((double)s1 * inv));
+                    z[o] = (float)((double)val * inv);
                 }
             }
         }
