@@ -52,21 +52,22 @@ __device__ __forceinline__ uint32_t lds_address(const void* p) {
     return (uint32_t)(size_t)(__attribute__((address_space(3))) const uint8_t*)p;
 }
 
-// Byte layout of a 64-bin histogram row: bin r sits in word r & 15, byte r >> 4, so the ~20
-// consecutive bins under a surface's return land in different words (and banks) instead of
-// five shared words, and the lanes adding them rarely collide on one address; the byte at
-// position p of a row holds bin row_bin(p).  The contraction only needs every A element and its
-// B element to name the same bin, so the V fragments are built with the same permutation.
-__device__ __forceinline__ int row_bin(int p) { return 16 * (p & 3) + (p >> 2); }
+// Byte layout of a 64-bin histogram row: bin r is byte r, so bin x (0 <= x < 64 J) sits in byte
+// x & 3 of the row's word (x & 63) >> 2.  Both the word address and the one-hot increment then take
+// two instructions each: the shift amount 8 (x & 3) is (x << 3) mod 32, which is what a 32-bit shift
+// uses of its amount.  (Spreading a surface's ~20 consecutive bins over more words, bin r in word
+// r & 15 and byte r >> 4, avoids some same-word atomics in one instruction but costs three more
+// instructions per photon, which measured slower.)  The V fragments follow the same order.
+__device__ __forceinline__ int row_bin(int p) { return p; }
 
-// Byte address of the 32-bit word that holds bin x (0 <= x < 64 J) in the histogram at hbase (a
-// multiple of 64): row x >> 6 starts at byte 80 (x >> 6).
+// Byte address of the 32-bit word that holds bin x in the histogram at hbase (a multiple of 64):
+// row x >> 6 starts at byte 80 (x >> 6).
 __device__ __forceinline__ uint32_t bin_word(uint32_t hbase, uint32_t x) {
-    return __builtin_amdgcn_ubfe(x, 6, 16) * (uint32_t)kRowPitch + (((x & 15u) << 2) | hbase);
+    return __builtin_amdgcn_ubfe(x, 6, 16) * (uint32_t)kRowPitch + ((x & 60u) | hbase);
 }
 
 // 1 in the byte of its word that holds bin x.
-__device__ __forceinline__ uint32_t bin_one(uint32_t x) { return 1u << ((x >> 1) & 24u); }
+__device__ __forceinline__ uint32_t bin_one(uint32_t x) { return 1u << ((x << 3) & 31u); }
 
 __device__ __forceinline__ void bin_add(uint32_t hbase, uint32_t x, uint32_t one) {
     __hip_atomic_fetch_add((lds_u32*)(size_t)bin_word(hbase, x), one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
