@@ -5,6 +5,7 @@ import itertools
 import numpy as np
 import pytest
 
+import synth
 from oracle import model as OM
 from oracle import srt3d as O
 
@@ -111,15 +112,47 @@ def test_data_step_noiseless_fixed_point_and_convergence():
     np.testing.assert_allclose(st.alpha, alpha, atol=1e-4)
 
 
-def test_step_sizes_closed_form():
-    T, m = 100, 3
-    p = O.Params(T, m, 2, eta_t=0.5, eta_a=2.0)
-    hhat = np.array([1.0, 0.5j, -0.25])
-    gt, ga = O.step_sizes(np.array([3, 40, 7]), hhat, p)
-    w = 2 * np.pi * np.arange(1, 4) / T
-    assert gt == pytest.approx(0.5 / (2 * 40 * (w[0] ** 2 + 0.25 * w[1] ** 2 + 0.0625 * w[2] ** 2)))
-    assert ga == pytest.approx(2.0 / (2 * 40 * 2 * (1 + 0.25 + 0.0625)))
-    assert O.step_sizes(np.zeros(3), hhat, p) == (0.0, 0.0)
+def test_step_sizes_are_the_curvature_of_the_data_term():
+    """The steps are eta / L with L bounds of the data term's curvature (reading 10).  At a
+    noiseless state with one point of intensity 1 in every pixel the bounds are attained: the
+    second differences of the loss along t and along alpha equal L_t and L_alpha.  With two
+    points and alpha in the simplex they bound the curvature: the t second differences and the
+    largest eigenvalue of the alpha-block Hessian stay below them."""
+    T, m, P = 256, 6, 40
+    rng = np.random.default_rng(3)
+    h, o = synth.binned_gaussian_irf(3.0)
+    hhat = OM.irf_spectrum(h, o, T, m)
+    n = np.full(P, 500)
+    for K in (1, 2):
+        p = O.Params(T, m, K, eta_t=0.7, eta_a=1.3)
+        gt, ga = O.step_sizes(n, hhat, p)
+        Lt, La = p.eta_t / gt, p.eta_a / ga
+        t = rng.uniform(0, T, (P, K))
+        act = np.ones((P, K), bool)
+        alpha = np.ones((P, K)) if K == 1 else rng.dirichlet([1.0] * K, P)
+        z = OM.model_sketch(t, alpha, act, hhat, T)
+        loss = lambda tt, aa: OM.loss(z, n, tt, aa, act, hhat, T)       # noqa: E731
+        e = 1e-3
+        L0 = loss(t, alpha)
+        d2t = np.empty((P, K))
+        H = np.empty((P, K, K))
+        for k in range(K):
+            d = np.zeros((P, K))
+            d[:, k] = e
+            d2t[:, k] = (loss(t + d, alpha) - 2 * L0 + loss(t - d, alpha)) / e**2
+            for j in range(K):
+                dj = np.zeros((P, K))
+                dj[:, j] = e
+                H[:, k, j] = (loss(t, alpha + d + dj) - loss(t, alpha + d - dj) - loss(t, alpha - d + dj)
+                              + loss(t, alpha - d - dj)) / (4 * e**2)
+        lam = np.linalg.eigvalsh(H).max(1)
+        if K == 1:
+            np.testing.assert_allclose(d2t[:, 0], Lt, rtol=1e-5)
+            np.testing.assert_allclose(lam, La, rtol=1e-6)
+        else:
+            assert np.all(d2t <= Lt * (1 + 1e-6)) and np.all(lam <= La * (1 + 1e-9))
+            assert d2t.max() > 0.2 * Lt and lam.max() > 0.3 * La          # and not vacuous
+    assert O.step_sizes(np.zeros(3), hhat, O.Params(T, m, 1)) == (0.0, 0.0)
 
 
 # ------------------------------------------------------------------ depth denoiser
