@@ -29,8 +29,8 @@ METRIC = "photons sketched/s + SRT3D frames/s (fraction of HBM roofline); p50/p9
 HBM_PEAK_GBS = 8000.0
 # per sketch method: (kernel name, its source file, the committed HBM-counter summary)
 SKETCH_KERNELS = {
-    "binned": ("sketch_binned_kernel", "binned.hip", "sketch_binned_{w}_traffic.md"),
-    "photon": ("sketch_photons_kernel", "sketch.hip", "sketch_photons_{w}_traffic.md"),
+    "binned": ("sketch_binned_kernel", "binned.hip", "traffic_{w}.md"),
+    "photon": ("sketch_photons_kernel", "sketch.hip", "traffic_{w}.md"),
 }
 
 
@@ -52,40 +52,41 @@ def parse():
     return ap.parse_args()
 
 
-def sketch_traffic(method: str, workload: str):
-    """HBM bytes per sketch launch from the committed counter summary, if it describes the
-    current kernel source (else None)."""
-    _, src, summary = SKETCH_KERNELS[method]
-    path = os.path.join(ROOT, "profiles", summary.format(w=workload))
+def profile_figure(summary: str, src: str, key: str):
+    """A figure from a committed rocprofv3 summary under profiles/ (the line `key: value`), if the
+    summary records the sha256 of the current kernel source `src` (else None: the counters were
+    taken on other code)."""
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     text = open(path).read()
     sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2203_00952_amd", "csrc", src), "rb").read()).hexdigest()
     m_sha = re.search(re.escape(src) + r" sha256:\s*([0-9a-f]{64})", text)
-    m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m_sha or not m_b or m_sha.group(1) != sha:
+    m_v = re.search(re.escape(key) + r":\s*([0-9.eE+]+)", text)
+    if not m_sha or not m_v or m_sha.group(1) != sha:
         return None
-    return float(m_b.group(1))
+    return float(m_v.group(1))
+
+
+def sketch_traffic(method: str, workload: str):
+    """HBM bytes per sketch launch from the committed counter summary (None if stale)."""
+    kernel, src, summary = SKETCH_KERNELS[method]
+    return profile_figure(summary.format(w=workload), src, f"{kernel} traffic_bytes_per_launch")
 
 
 VALU_PEAK = 256 * 2.4e9        # wave64 VALU instructions per second: one per clock per CU
 
 
-def sketch_valu(method: str, workload: str):
-    """VALU wave instructions per binned-sketch launch from the committed counter summary of the
-    throughput workload, if it describes the current kernel source (else None)."""
-    if method != "binned" or workload != "throughput":
-        return None
-    path = os.path.join(ROOT, "profiles", "valu_counters_throughput.md")
-    if not os.path.exists(path):
-        return None
-    text = open(path).read()
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2203_00952_amd", "csrc", "binned.hip"), "rb").read()).hexdigest()
-    m_sha = re.search(r"binned\.hip sha256:\s*([0-9a-f]{64})", text)
-    m_v = re.search(r"sketch_binned_kernel VALU wave instructions per launch:\s*([0-9.eE+]+)", text)
-    if not m_sha or not m_v or m_sha.group(1) != sha:
-        return None
-    return float(m_v.group(1))
+def valu_per_launch(kernel: str, src: str, workload: str):
+    """VALU wave instructions per launch of `kernel` from the committed counter summary of the
+    workload (None if stale or absent)."""
+    return profile_figure(f"valu_counters_{workload}.md", src, f"{kernel} VALU wave instructions per launch")
+
+
+def iteration_bytes_per_pixel(m: int, K: int) -> float:
+    """Algorithmic HBM bytes per pixel of one fused iteration: the sketch (8 m) and the photon count
+    (4) in, the point state (t and alpha, 4 B each per point, and the activity word) in and out."""
+    return 8.0 * m + 4.0 + 2.0 * (8.0 * K + 4.0)
 
 
 def _oracle_sketch_chunk(args):
@@ -472,8 +473,22 @@ def main():
     alg_bytes = 4.0 * N + 8.0 * (P + 1) + 8.0 * m * P + 4.0 * P
     achieved = alg_bytes / (sk_ms.mean() * 1e-3) / 1e9
     traffic = sketch_traffic(args.sketch, w.name)
-    valu = sketch_valu(args.sketch, w.name)
+    valu = valu_per_launch(SKETCH_KERNELS[args.sketch][0], SKETCH_KERNELS[args.sketch][1], w.name)
     kernel = SKETCH_KERNELS[args.sketch][0]
+
+    # the fused iteration alone (outside the timed steps, on the stream it is launched on): the
+    # average launch of `iters` back-to-back iterations from the last step's state
+    e_i = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    rec.iterate(z, n, params.iters)
+    e_i[0].record(stream)
+    rec.iterate(z, n, params.iters)
+    e_i[1].record(stream)
+    torch.cuda.synchronize()
+    it_ms = e_i[0].elapsed_time(e_i[1]) / params.iters
+    it_bytes = iteration_bytes_per_pixel(m, w.K_max) * P
+    it_achieved = it_bytes / (it_ms * 1e-3) / 1e9
+    it_traffic = profile_figure(f"traffic_{w.name}.md", "srt3d.hip", "iteration_kernel traffic_bytes_per_launch")
+    it_valu = valu_per_launch("iteration_kernel", "srt3d.hip", w.name)
 
     # achievable HBM bandwidth on this device: a plain 1 GiB device-to-device copy (reads and
     # writes 1 GiB each), outside the timed steps
@@ -603,17 +618,27 @@ def main():
         "srt3d_ms": {"mean": float(rc_ms.mean()), "p50": float(np.percentile(rc_ms, 50)),
                      "p99": float(np.percentile(rc_ms, 99))},
         "latency_ms": {"p50": float(np.percentile(st_ms, 50)), "p99": float(np.percentile(st_ms, 99))},
-        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
-                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
-        # the same kernel against its binding limit, VALU issue (counts from the committed
-        # rocprofv3 summary, the time live)
-        "valu_roofline": None if valu is None else {
-            "kernel": kernel, "valu_wave_insts_per_launch": valu,
-            "achieved": valu / (sk_ms.mean() * 1e-3), "peak": VALU_PEAK, "unit": "wave instructions/s",
-            "frac": valu / (sk_ms.mean() * 1e-3) / VALU_PEAK},
+        "roofline_sketch": {"bound": "hbm", "kernel": kernel, "achieved": achieved,
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                            "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
+                            "launch_ms": float(sk_ms.mean()), "launches_per_step": 1,
+                            "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                            # against its binding limit, VALU issue (counts from the committed
+                            # rocprofv3 summary, the time live)
+                            "valu_issue_frac": None if valu is None else valu / (sk_ms.mean() * 1e-3) / VALU_PEAK,
+                            "valu_wave_insts_per_launch": valu},
+        "roofline_iteration": {"bound": "hbm", "kernel": "iteration_kernel", "achieved": it_achieved,
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": it_achieved / HBM_PEAK_GBS,
+                               "traffic": it_traffic, "algorithmic_bytes_per_launch": it_bytes,
+                               "launch_ms": it_ms, "launches_per_step": params.iters,
+                               "copy_gbs": copy_gbs, "frac_of_copy": it_achieved / copy_gbs,
+                               "valu_issue_frac": None if it_valu is None else it_valu / (it_ms * 1e-3) / VALU_PEAK,
+                               "valu_wave_insts_per_launch": it_valu},
     }
+    # the dominant kernel of the step (launch time x launches per step) is the line's roofline
+    share = {k: res[k]["launch_ms"] * res[k]["launches_per_step"] for k in ("roofline_sketch", "roofline_iteration")}
+    res["roofline"] = dict(res[max(share, key=share.get)])
+    res["roofline"]["step_share"] = max(share.values()) / ms_per_step
     # the serving workload's request stream, short (outside the timed steps): p50/p99 latency
     # under Poisson arrivals at 0.5x and 0.9x of the measured single-slot capacity
     if args.serving_requests > 0:
