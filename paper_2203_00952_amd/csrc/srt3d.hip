@@ -1232,8 +1232,10 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
 //
 // wprep_kernel: one segment of M2 >= 2m lanes per pixel; Sigma and its Cholesky factor as in the
 // weighted pixelwise fit, the rows of L^{-1} by forward substitution of the unit vectors, then
-// W_ij = sum_k (L^{-1})_ki (L^{-1})_kj through LDS; lane i writes row i of W_p ([P][2m][2m], FP32)
-// and the frame's n_w is an atomic maximum of the (non-negative) float bits.
+// W_ij = sum_k (L^{-1})_ki (L^{-1})_kj through LDS (the same bits for W_ji: same products, same
+// order), and the frame's n_w is an atomic maximum of the (non-negative) float bits.  W_p is
+// [P][2m][2m] FP32; lane i writes column i (W_ji = W_ij), so the lanes of one store write
+// consecutive words.
 template <int K, int M2>
 __global__ __launch_bounds__(256) void wprep_kernel(IterArgs A, const int32_t* __restrict__ n,
                                                     const float2* __restrict__ h2, const float* __restrict__ t_in,
@@ -1270,11 +1272,11 @@ __global__ __launch_bounds__(256) void wprep_kernel(IterArgs A, const int32_t* _
     __syncthreads();
     float gsum = 0.f;
     if (i < twom) {
-        float* wrow = W + ((int64_t)pix * twom + i) * twom;
+        float* wcol = W + (int64_t)pix * twom * twom + i;
         for (int j = 0; j < twom; ++j) {
             float acc = 0.f;
             for (int k = i > j ? i : j; k < twom; ++k) acc = fmaf(sl[k][i], sl[k][j], acc);
-            if (valid) wrow[j] = acc;
+            if (valid) wcol[(int64_t)j * twom] = acc;
             gsum += fabsf(acc);
         }
     }
@@ -1284,7 +1286,8 @@ __global__ __launch_bounds__(256) void wprep_kernel(IterArgs A, const int32_t* _
 }
 
 // One weighted data step of every pixel, in place on the current half: lane i < 2m of the pixel's
-// segment holds row i of W_p; v = W e through one broadcast and one FMA per column.
+// segment holds row i of W_p, read as column i (W_p is symmetric), so that the lanes of one load
+// read consecutive words; v = W e through one broadcast and one FMA per column.
 template <int K, int M2>
 __global__ __launch_bounds__(256) void wdata_kernel(IterArgs A, const float* __restrict__ z,
                                                     const int32_t* __restrict__ n, const float2* __restrict__ hhat,
@@ -1310,9 +1313,9 @@ __global__ __launch_bounds__(256) void wdata_kernel(IterArgs A, const float* __r
         on[k] = act[q] != 0;
     }
     float wrow[M2];
-    const float* wp = W + ((int64_t)pix * twom + (i < twom ? i : 0)) * twom;
+    const float* wp = W + (int64_t)pix * twom * twom + (i < twom ? i : 0);
 #pragma unroll
-    for (int c = 0; c < M2; ++c) wrow[c] = (i < twom && c < twom) ? wp[c] : 0.f;
+    for (int c = 0; c < M2; ++c) wrow[c] = (i < twom && c < twom) ? wp[(int64_t)c * twom] : 0.f;
     // the W = I steps with n_max replaced by n_w
     const float nw = __uint_as_float(*nw_bits);
     const float gam_t = nw > 0.f ? scal[1] * (scal[0] / nw) : 0.f;
