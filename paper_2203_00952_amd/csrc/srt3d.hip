@@ -930,14 +930,21 @@ __global__ __launch_bounds__(1024) void spectrum_kernel(const double* __restrict
 }
 
 // A wave holds 64 / M2 pixels, one per segment of M2 lanes (M2 = 64: one pixel).  Broadcast of
-// lane `base + j` of the caller's segment: readlane when the segment is the wave, else a
+// lane `base + j` of the caller's segment: readlane when the segment is the wave; with two
+// segments, one readlane per segment and a select (scalar reads, no LDS traffic: the broadcasts
+// of the factorisation and the whitening outnumber the arithmetic); with more segments a
 // cross-lane permute through the LDS crossbar (one instruction for every segment).
 template <int M2>
 __device__ __forceinline__ float sbcast(float v, int base, int j) {
-    if constexpr (M2 == 64)
+    if constexpr (M2 == 64) {
         return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), j));
-    else
+    } else if constexpr (M2 == 32) {
+        const float lo = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), j));
+        const float hi = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32 + j));
+        return base == 0 ? lo : hi;
+    } else {
         return __shfl(v, base + j, 64);
+    }
 }
 
 // Sum over the caller's segment of M2 lanes (identical in all of them).
@@ -993,31 +1000,87 @@ __device__ __forceinline__ void w_forward(const float (&row)[M2], const float (&
     }
 }
 
-// In place: b <- Linv b with lane i holding row i of Linv (lower triangular): a broadcast and an
-// FMA per column.
+// Row pitch (floats) of a segment's M2 x M2 LDS matrix: unpadded, so that four waves of two
+// 32-lane segments fit four workgroups per CU; rows start on 16-byte boundaries and the lanes of
+// a segment writing one column hit consecutive words.
+template <int M2> constexpr int kLdsPitch = M2;
+// A segment's LDS matrix with 32 words of padding after it, so that the two segments of a wave
+// (M2 = 32) sit 32 banks apart and their simultaneous accesses do not collide.
+template <int M2> constexpr int kLdsSegment = M2 * kLdsPitch<M2> + 32;
+
+// Rows of L^{-1} (lower triangular) for the segment: lane i gets row i in linv.  Lane i solves
+// L x = e_i, i.e. column i of L^{-1}, by forward substitution with the rows of L read from LDS
+// (the lanes of a segment read the same entries, four at a time: broadcast reads, no cross-lane
+// permutes), then the columns are transposed through the same LDS.  sl: the segment's
+// M2 x kLdsPitch<M2> floats, 16-byte aligned, private to the wave.
+template <int M2>
+__device__ __forceinline__ void w_inverse_rows(const float (&row)[M2], const float (&invd)[M2], float (&linv)[M2],
+                                               int i, float* sl) {
+    constexpr int LP = kLdsPitch<M2>;
+#pragma unroll
+    for (int c = 0; c < M2; c += 4)       // row i of L (its entries c < i are read)
+        *reinterpret_cast<float4*>(sl + i * LP + c) = make_float4(row[c], row[c + 1], row[c + 2], row[c + 3]);
+    float x[M2];
+#pragma unroll
+    for (int c = 0; c < M2; ++c) {
+        float acc = c == i ? 1.f : 0.f;
+#pragma unroll
+        for (int k = 0; k < c; k += 4) {
+            const float4 q = *reinterpret_cast<const float4*>(sl + c * LP + k);
+            acc -= q.x * x[k];
+            if (k + 1 < c) acc -= q.y * x[k + 1];
+            if (k + 2 < c) acc -= q.z * x[k + 2];
+            if (k + 3 < c) acc -= q.w * x[k + 3];
+        }
+        x[c] = acc * invd[c];
+    }
+    // x[c] = (L^{-1})_{c i}; the reads above precede these writes in the wave's LDS order
+#pragma unroll
+    for (int c = 0; c < M2; ++c) sl[c * LP + i] = x[c];
+#pragma unroll
+    for (int c = 0; c < M2; c += 4) {
+        const float4 q = *reinterpret_cast<const float4*>(sl + i * LP + c);
+        linv[c] = q.x;
+        linv[c + 1] = q.y;
+        linv[c + 2] = q.z;
+        linv[c + 3] = q.w;
+    }
+}
+
+// In place: b <- Linv b for V vectors, lane i holding row i of Linv: each vector is written to
+// LDS once and read back whole by every lane of the segment (broadcast reads, four at a time),
+// one FMA per column.  sb: the segment's V x M2 floats, 16-byte aligned, private to the wave.
 template <int M2, int V>
-__device__ __forceinline__ void w_apply_inverse(const float (&linv)[M2], float (&b)[V], int base) {
-    float y[V];
+__device__ __forceinline__ void w_apply_inverse(const float (&linv)[M2], float (&b)[V], int i, float* sb) {
 #pragma unroll
-    for (int v = 0; v < V; ++v) y[v] = 0.f;
+    for (int v = 0; v < V; ++v) sb[v * M2 + i] = b[v];
 #pragma unroll
-    for (int c = 0; c < M2; ++c)
+    for (int v = 0; v < V; ++v) {
+        float y = 0.f;
 #pragma unroll
-        for (int v = 0; v < V; ++v) y[v] += linv[c] * sbcast<M2>(b[v], base, c);
-#pragma unroll
-    for (int v = 0; v < V; ++v) b[v] = y[v];
+        for (int c = 0; c < M2; c += 4) {
+            const float4 q = *reinterpret_cast<const float4*>(sb + v * M2 + c);
+            y = fmaf(linv[c], q.x, y);
+            y = fmaf(linv[c + 1], q.y, y);
+            y = fmaf(linv[c + 2], q.z, y);
+            y = fmaf(linv[c + 3], q.w, y);
+        }
+        b[v] = y;
+    }
 }
 
 // Whitening b <- L^{-1} b: with rows of up to 32 entries through the explicit inverse (formed
 // once per pixel), wider rows by forward substitution (the inverse would not fit in registers).
+// lds: the segment's M2 x kLdsPitch<M2> floats (used by the inverse form only).
 template <int M2>
 struct Whitener {
     static constexpr bool kInverse = M2 <= 32;
     float row[M2], invd[M2];
     float linv[kInverse ? M2 : 1];
     template <int V>
-    __device__ __forceinline__ void apply(float (&b)[V], int i, int base) const {
-        if constexpr (kInverse) w_apply_inverse<M2, V>(linv, b, base);
+    __device__ __forceinline__ void apply(float (&b)[V], int i, int base, float* lds) const {
+        static_assert(V <= M2 + 4, "the vectors fit the segment's LDS matrix");
+        if constexpr (kInverse) w_apply_inverse<M2, V>(linv, b, i, lds);
         else w_forward<M2, V>(row, invd, b, i, base);
     }
 };
@@ -1100,13 +1163,14 @@ __device__ __forceinline__ void w_factor(const float2* __restrict__ h2, int i, i
 }
 
 template <int K, int M2>
-__global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, const float* __restrict__ z,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 4 : 1))) void wsmle_kernel(IterArgs A, int witers, const float* __restrict__ z,
                                                     const int32_t* __restrict__ n, const float2* __restrict__ h2,
                                                     float* __restrict__ t_io, float* __restrict__ a_io,
                                                     const uint8_t* __restrict__ act, float* __restrict__ loss_out) {
     constexpr int kWaves = 256 / 64;
     constexpr int kPPW = 64 / M2;                      // pixels per wave, one per segment
     __shared__ float2 s_psi[kWaves][kPPW][2 * M2 + 1];
+    __shared__ __align__(16) float s_lw[kWaves][kPPW][Whitener<M2>::kInverse ? kLdsSegment<M2> : 4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int seg = lane / M2, i = lane % M2, base = seg * M2;
     const int pix_raw = (blockIdx.x * kWaves + wv) * kPPW + seg;
@@ -1114,6 +1178,7 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
     const int pix = valid ? pix_raw : A.P - 1;
     const int m = A.m, T = A.T;
     const float Tf = (float)T, invT = 1.0f / Tf, twoinvT = 2.0f / Tf;
+    float* lw = s_lw[wv][seg];
     float tk[K], ak[K];
     bool on[K];
 #pragma unroll
@@ -1125,19 +1190,14 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
     }
     Whitener<M2> wh;
     w_factor<K, M2>(h2, i, base, m, T, tk, ak, on, s_psi[wv][seg], wh);
-    if constexpr (Whitener<M2>::kInverse) {
-        // lane i: row i of L^{-1}, the forward substitution of the unit vectors
-#pragma unroll
-        for (int v = 0; v < M2; ++v) wh.linv[v] = i == v ? 1.f : 0.f;
-        w_forward<M2, M2>(wh.row, wh.invd, wh.linv, i, base);
-    }
+    if constexpr (Whitener<M2>::kInverse) w_inverse_rows<M2>(wh.row, wh.invd, wh.linv, i, lw);   // lane i: row i
     const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m);
     const float nq = (float)n[pix];
     auto loss_at = [&](const float* tt, const float* aa) {
         float b[1];
         float jc[2 * K];
         w_residual<K>(zp, h2, i, m, T, tt, aa, on, b[0], jc);
-        wh.apply(b, i, base);
+        wh.apply(b, i, base, lw);
         return nq * seg_sum<M2>(b[0] * b[0]);
     };
     float loss = loss_at(tk, ak);
@@ -1151,7 +1211,7 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
             w_residual<K>(zp, h2, i, m, T, tk, ak, on, b[0], jc);
 #pragma unroll
             for (int c = 0; c < 2 * K; ++c) b[1 + c] = jc[c];
-            wh.apply(b, i, base);
+            wh.apply(b, i, base, lw);
             // normal equations (identical in every lane of the segment)
             float Am[2 * K][2 * K], g[2 * K];
 #pragma unroll
@@ -1237,14 +1297,16 @@ __global__ __launch_bounds__(256) void wsmle_kernel(IterArgs A, int witers, cons
 // [P][2m][2m] FP32; lane i writes column i (W_ji = W_ij), so the lanes of one store write
 // consecutive words.
 template <int K, int M2>
-__global__ __launch_bounds__(256) void wprep_kernel(IterArgs A, const int32_t* __restrict__ n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 4 : 1))) void wprep_kernel(IterArgs A, const int32_t* __restrict__ n,
                                                     const float2* __restrict__ h2, const float* __restrict__ t_in,
                                                     const float* __restrict__ a_in, const uint8_t* __restrict__ act,
                                                     float* __restrict__ W, unsigned int* __restrict__ nw_bits) {
     constexpr int kWaves = 256 / 64;
     constexpr int kPPW = 64 / M2;
     __shared__ float2 s_psi[kWaves][kPPW][2 * M2 + 1];
-    __shared__ float s_li[kWaves][kPPW][M2][M2 + 1];
+    // rows of L^{-1}: unpadded as the inverse leaves them, padded by one word when written here
+    constexpr int LP = Whitener<M2>::kInverse ? kLdsPitch<M2> : M2 + 1;
+    __shared__ __align__(16) float s_li[kWaves][kPPW][Whitener<M2>::kInverse ? kLdsSegment<M2> : M2 * LP];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int seg = lane / M2, i = lane % M2, base = seg * M2;
     const int pix_raw = (blockIdx.x * kWaves + wv) * kPPW + seg;
@@ -1263,16 +1325,50 @@ __global__ __launch_bounds__(256) void wprep_kernel(IterArgs A, const int32_t* _
     Whitener<M2> wh;
     w_factor<K, M2>(h2, i, base, m, A.T, tk, ak, on, s_psi[wv][seg], wh);
     float li[M2];
+    float (*sl)[LP] = reinterpret_cast<float (*)[LP]>(s_li[wv][seg]);
+    if constexpr (Whitener<M2>::kInverse) {
+        w_inverse_rows<M2>(wh.row, wh.invd, li, i, &sl[0][0]);      // leaves L^{-1} in sl, row-major
+    } else {
 #pragma unroll
-    for (int v = 0; v < M2; ++v) li[v] = i == v ? 1.f : 0.f;
-    w_forward<M2, M2>(wh.row, wh.invd, li, i, base);
-    float (*sl)[M2 + 1] = s_li[wv][seg];
+        for (int v = 0; v < M2; ++v) li[v] = i == v ? 1.f : 0.f;
+        w_forward<M2, M2>(wh.row, wh.invd, li, i, base);
 #pragma unroll
-    for (int c = 0; c < M2; ++c) sl[i][c] = li[c];
+        for (int c = 0; c < M2; ++c) sl[i][c] = li[c];
+    }
     __syncthreads();
     float gsum = 0.f;
-    if (i < twom) {
-        float* wcol = W + (int64_t)pix * twom * twom + i;
+    float* wcol = W + (int64_t)pix * twom * twom + i;
+    if constexpr (Whitener<M2>::kInverse) {
+        // All of row i at once: for each k, entry (k, i) of L^{-1} and row k read four entries
+        // at a time by the whole segment (broadcast reads).  The products with k < max(i, j) or
+        // k >= 2m are exact zeros (L^{-1} is lower triangular with identity rows past 2m), so each
+        // sum is the one over k = max(i, j) .. 2m - 1 in the same order, and W_ij and W_ji the
+        // same bits.  (The k loop stays rolled: unrolled, the reads of every row are hoisted.)
+        float acc[M2];
+#pragma unroll
+        for (int j = 0; j < M2; ++j) acc[j] = 0.f;
+#pragma unroll 1
+        for (int k = 0; k < M2; ++k) {
+            const float xk = sl[k][i];
+#pragma unroll
+            for (int j = 0; j < M2; j += 4) {
+                const float4 q = *reinterpret_cast<const float4*>(&sl[k][j]);
+                acc[j] = fmaf(xk, q.x, acc[j]);
+                acc[j + 1] = fmaf(xk, q.y, acc[j + 1]);
+                acc[j + 2] = fmaf(xk, q.z, acc[j + 2]);
+                acc[j + 3] = fmaf(xk, q.w, acc[j + 3]);
+            }
+        }
+        if (i < twom) {
+#pragma unroll
+            for (int j = 0; j < M2; ++j) {
+                if (j < twom) {
+                    if (valid) wcol[(int64_t)j * twom] = acc[j];
+                    gsum += fabsf(acc[j]);
+                }
+            }
+        }
+    } else if (i < twom) {
         for (int j = 0; j < twom; ++j) {
             float acc = 0.f;
             for (int k = i > j ? i : j; k < twom; ++k) acc = fmaf(sl[k][i], sl[k][j], acc);
