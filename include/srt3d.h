@@ -371,8 +371,9 @@ int srt3d_smle_weighted(const float* d_z, const int32_t* d_n, const double* d_ir
  * c n_max when every W_p = c I, so that case is exactly SRT3D).  The denoisers are SRT3D's.
  * srt3d_weighted_prepare: W_p from the current half of st (normally right after srt3d_init,
  *   whose hhat and scal it needs) and n_w, into d_ws (srt3d_workspace_bytes(p, P,
- *   SRT3D_CALL_WEIGHTED_ITERATE) bytes, 256-byte aligned: 4 (2m)^2 bytes per pixel); the impulse
- *   response as for srt3d_init.
+ *   SRT3D_CALL_WEIGHTED_ITERATE) bytes, 256-byte aligned: per pixel the lower triangle of the
+ *   symmetric 2m x 2m W_p by columns, d (d + 1) / 2 floats (d = 2m) rounded up to a multiple of
+ *   4); the impulse response as for srt3d_init.
  * srt3d_weighted_step: one weighted data step, in place (st->cur unchanged).
  * srt3d_weighted_iterate: `iters` x (weighted data step, depth denoiser, intensity denoiser);
  *   st->cur is unchanged after each iteration.

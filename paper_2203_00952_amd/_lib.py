@@ -491,10 +491,14 @@ class Reconstructor:
                "srt3d_weighted_iterate")
 
     def weighted_matrices(self):
-        """W_p from the weighted workspace as [P, 2m, 2m] (a view), and the frame bound n_w."""
+        """W_p from the weighted workspace as stored (a view): [P, tri] FP32, each row the lower
+        triangle of the symmetric d x d matrix (d = 2m) by columns -- column c holds W_ic,
+        i = c .. d - 1, from offset c d - c (c - 1) / 2 -- padded to tri = d (d + 1) / 2 rounded
+        up to a multiple of 4; and the frame bound n_w."""
         P, d = self.p.P, 2 * self.p.m
+        tri = (d * (d + 1) // 2 + 3) & ~3
         off = 256 + (d * 8 + 255) // 256 * 256
-        W = self.wws[off:off + P * d * d * 4].view(torch.float32).view(P, d, d)
+        W = self.wws[off:off + P * tri * 4].view(torch.float32).view(P, tri)
         nw = self.wws[:4].view(torch.float32)
         return W, nw
 

@@ -1283,6 +1283,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 
 }
 
 // ----------------------------------------------------------------------------- weighted SRT3D
+// W_p is stored as its lower triangle by columns: column c holds W_ic for i = c .. d - 1
+// (d = 2m), at offset c d - c (c - 1) / 2 of the pixel's block; blocks of d (d + 1) / 2 floats
+// rounded up to a multiple of four (16-byte aligned).  Half of the full matrix's bytes, and the
+// entries of one column are consecutive.
+__host__ __device__ constexpr int w_tri(int d) { return ((d * (d + 1) / 2) + 3) & ~3; }
+__host__ __device__ constexpr int w_col(int d, int c) { return c * d - c * (c - 1) / 2; }
+
 // Eq. (8) with a per-pixel W inside SRT3D's data step: W_p = Sigma(theta_0)^{-1}, the inverse of
 // the ridged covariance of the sketch's 2m real coordinates at the pixel's points theta_0 (the
 // state when prepared, normally the initialisation), held fixed.  The data step is SRT3D's with
@@ -1293,9 +1300,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 
 // wprep_kernel: one segment of M2 >= 2m lanes per pixel; Sigma and its Cholesky factor as in the
 // weighted pixelwise fit, the rows of L^{-1} by forward substitution of the unit vectors, then
 // W_ij = sum_k (L^{-1})_ki (L^{-1})_kj through LDS (the same bits for W_ji: same products, same
-// order), and the frame's n_w is an atomic maximum of the (non-negative) float bits.  W_p is
-// [P][2m][2m] FP32; lane i writes column i (W_ji = W_ij), so the lanes of one store write
-// consecutive words.
+// order), and the frame's n_w is an atomic maximum of the (non-negative) float bits.  Lane i
+// writes the entries W_ij, j <= i, of its row: the lanes of one store (one j) write consecutive
+// words of column j of the packed lower triangle.
 template <int K, int M2>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 4 : 1))) void wprep_kernel(IterArgs A, const int32_t* __restrict__ n,
                                                     const float2* __restrict__ h2, const float* __restrict__ t_in,
@@ -1337,7 +1344,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 
     }
     __syncthreads();
     float gsum = 0.f;
-    float* wcol = W + (int64_t)pix * twom * twom + i;
+    float* wtri = W + (int64_t)pix * w_tri(twom);
     if constexpr (Whitener<M2>::kInverse) {
         // All of row i at once: for each k, entry (k, i) of L^{-1} and row k read four entries
         // at a time by the whole segment (broadcast reads).  The products with k < max(i, j) or
@@ -1363,7 +1370,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 
 #pragma unroll
             for (int j = 0; j < M2; ++j) {
                 if (j < twom) {
-                    if (valid) wcol[(int64_t)j * twom] = acc[j];
+                    if (valid && j <= i) wtri[w_col(twom, j) + (i - j)] = acc[j];
                     gsum += fabsf(acc[j]);
                 }
             }
@@ -1372,7 +1379,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 
         for (int j = 0; j < twom; ++j) {
             float acc = 0.f;
             for (int k = i > j ? i : j; k < twom; ++k) acc = fmaf(sl[k][i], sl[k][j], acc);
-            if (valid) wcol[(int64_t)j * twom] = acc;
+            if (valid && j <= i) wtri[w_col(twom, j) + (i - j)] = acc;
             gsum += fabsf(acc);
         }
     }
@@ -1381,9 +1388,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 
     if (valid && i == 0) atomicMax(nw_bits, __float_as_uint(gsum * (float)n[pix]));
 }
 
-// One weighted data step of every pixel, in place on the current half: lane i < 2m of the pixel's
-// segment holds row i of W_p, read as column i (W_p is symmetric), so that the lanes of one load
-// read consecutive words; v = W e through one broadcast and one FMA per column.
+// One weighted data step of every pixel, in place on the current half: the wave's packed
+// triangles (consecutive pixels, so one contiguous range) are copied to LDS by 16-byte loads,
+// then lane i < 2m of the pixel's segment reads row i of W_p from there (W_ic from column c for
+// c <= i, from column i for c > i); v = W e through one broadcast and one FMA per column.
 template <int K, int M2>
 __global__ __launch_bounds__(256) void wdata_kernel(IterArgs A, const float* __restrict__ z,
                                                     const int32_t* __restrict__ n, const float2* __restrict__ hhat,
@@ -1409,23 +1417,46 @@ __global__ __launch_bounds__(256) void wdata_kernel(IterArgs A, const float* __r
         on[k] = act[q] != 0;
     }
     float wrow[M2];
-    const float* wp = W + (int64_t)pix * twom * twom + (i < twom ? i : 0);
+    {
+        constexpr int kMaxTri = w_tri(M2);
+        __shared__ __align__(16) float s_w[kWaves][kPPW * kMaxTri];
+        const int tri = w_tri(twom);                         // floats per pixel, a multiple of 4
+        const int p0 = (blockIdx.x * kWaves + wv) * kPPW;    // the wave's first pixel
+        const int np = A.P - p0 < kPPW ? A.P - p0 : kPPW;     // its pixels in the frame (>= 1)
+        const float4* src = reinterpret_cast<const float4*>(W + (int64_t)p0 * tri);
+        float4* dst = reinterpret_cast<float4*>(s_w[wv]);
+        for (int q = lane; q < np * tri / 4; q += 64) dst[q] = src[q];
+        const float* tw = s_w[wv] + (valid ? seg : 0) * tri;  // (same wave: LDS order suffices)
 #pragma unroll
-    for (int c = 0; c < M2; ++c) wrow[c] = (i < twom && c < twom) ? wp[(int64_t)c * twom] : 0.f;
+        for (int c = 0; c < M2; ++c) {
+            float v = 0.f;
+            if (i < twom && c < twom) v = c <= i ? tw[w_col(twom, c) + (i - c)] : tw[w_col(twom, i) + (c - i)];
+            wrow[c] = v;
+        }
+    }
     // the W = I steps with n_max replaced by n_w
     const float nw = __uint_as_float(*nw_bits);
     const float gam_t = nw > 0.f ? scal[1] * (scal[0] / nw) : 0.f;
     const float gam_a = nw > 0.f ? scal[2] * (scal[0] / nw) : 0.f;
     const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m);
     const float nq = (float)n[pix];
-    // g = 2 n J^T W e at (tt, ak)
+    // g = 2 n J^T W e at (tt, ak); e goes to LDS once and every lane of the segment reads it
+    // whole, four entries at a time (broadcast reads)
+    __shared__ __align__(16) float s_e[kWaves][64];
+    float* se = s_e[wv] + base;
     auto grad = [&](const float* tt, float* g) {
         float r, jc[2 * K];
         w_residual<K>(zp, hhat, i, m, T, tt, ak, on, r, jc);          // r = z - Phi
-        const float e = -r;
+        se[i] = -r;                                                    // e
         float v = 0.f;
 #pragma unroll
-        for (int c = 0; c < M2; ++c) v = fmaf(wrow[c], sbcast<M2>(e, base, c), v);
+        for (int c = 0; c < M2; c += 4) {
+            const float4 q = *reinterpret_cast<const float4*>(se + c);
+            v = fmaf(wrow[c], q.x, v);
+            v = fmaf(wrow[c + 1], q.y, v);
+            v = fmaf(wrow[c + 2], q.z, v);
+            v = fmaf(wrow[c + 3], q.w, v);
+        }
 #pragma unroll
         for (int c = 0; c < 2 * K; ++c) g[c] = 2.f * nq * seg_sum<M2>(jc[c] * v);
     };
@@ -2171,13 +2202,14 @@ hipError_t launch_wsmle(const srt3d_params& p, const double* irf, int irf_len, i
     return hipGetLastError();
 }
 
-// weighted-SRT3D workspace: n_w (256 bytes), the spectrum to harmonic 2m, then W [P][2m][2m]
+// weighted-SRT3D workspace: n_w (256 bytes), the spectrum to harmonic 2m, then W's packed lower
+// triangles [P][w_tri(2m)]
 static size_t wsrt_spec_offset() { return 256; }
 static size_t wsrt_w_offset(const srt3d_params& p) {
     return wsrt_spec_offset() + (((size_t)2 * p.m * sizeof(float2) + 255) & ~(size_t)255);
 }
 size_t wsrt_ws_bytes(const srt3d_params& p) {
-    return wsrt_w_offset(p) + (size_t)p.rows * p.cols * (2 * p.m) * (2 * p.m) * sizeof(float);
+    return wsrt_w_offset(p) + (size_t)p.rows * p.cols * w_tri(2 * p.m) * sizeof(float);
 }
 
 hipError_t launch_wsrt_prepare(const srt3d_params& p, const double* irf, int irf_len, int irf_origin,

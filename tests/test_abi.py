@@ -76,6 +76,14 @@ def test_workspace_and_state_size_queries(lib):
     assert ws(L.CALLS["reconstruct"], P + 1) == 0           # P must match rows * cols
     assert ws(99) == 0
     up = lambda b: (b + 255) // 256 * 256                   # noqa: E731
+    # weighted SRT3D: n_w, the spectrum to harmonic 2m, then per pixel W's lower triangle by
+    # columns, d (d + 1) / 2 floats (d = 2m) rounded up to a multiple of 4
+    for m in (16, 5):
+        lib.srt3d_params_default(ctypes.byref(p), 256, 256, 4096, m, 1)
+        d = 2 * m
+        tri = (d * (d + 1) // 2 + 3) // 4 * 4
+        assert ws(L.CALLS["weighted_iterate"]) == 256 + up(d * 8) + P * tri * 4
+    lib.srt3d_params_default(ctypes.byref(p), 256, 256, 4096, 16, 1)
     for K in (1, 2, 3):
         p.K_max = K
         PK = P * K

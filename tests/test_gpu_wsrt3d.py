@@ -26,6 +26,17 @@ CASES = {
 }
 
 
+def unpack_lower(packed, d):
+    """The symmetric [P, d, d] matrices from their lower triangles stored by columns (column c:
+    entries c .. d - 1, from offset c d - c (c - 1) / 2)."""
+    W = np.zeros((packed.shape[0], d, d))
+    for c in range(d):
+        o = c * d - c * (c - 1) // 2
+        W[:, c:, c] = packed[:, o:o + d - c]
+        W[:, c, c:] = packed[:, o:o + d - c]
+    return W
+
+
 class Setup:
     def __init__(self, name, dev, iters=50):
         spec, m, K, r_min = CASES[name]
@@ -72,9 +83,9 @@ def test_weights_and_frame_bound(name):
     s = Setup(name, dev)
     st0 = s.oracle_init()
     s.gpu_prepare_from(st0)
-    Wg, nwg = s.rec.weighted_matrices()
+    Wp, nwg = s.rec.weighted_matrices()
     torch.cuda.synchronize()
-    Wg = Wg.cpu().numpy().astype(np.float64)
+    Wg = unpack_lower(Wp.cpu().numpy().astype(np.float64), 2 * s.m)
     S = OWP.covariance(st0.t, st0.alpha, st0.active, s.hhat2, s.spec.T, s.m)
     d = 2 * s.m
     tr = np.trace(S, axis1=1, axis2=2)
