@@ -986,20 +986,6 @@ __device__ __forceinline__ void w_residual(const float2* __restrict__ zp, const 
     r = re ? zl.x - phi.x : zl.y - phi.y;
 }
 
-// In place: b <- L^{-1} b for V vectors held one entry per lane (row i of the segment at base).
-template <int M2, int V>
-__device__ __forceinline__ void w_forward(const float (&row)[M2], const float (&invd)[M2], float (&b)[V], int i,
-                                          int base) {
-#pragma unroll
-    for (int c = 0; c < M2; ++c) {
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const float y = sbcast<M2>(b[v], base, c) * invd[c];
-            b[v] = i == c ? y : (i > c ? b[v] - row[c] * y : b[v]);
-        }
-    }
-}
-
 // Row pitch (floats) of a segment's M2 x M2 LDS matrix: unpadded, so that four waves of two
 // 32-lane segments fit four workgroups per CU; rows start on 16-byte boundaries and the lanes of
 // a segment writing one column hit consecutive words.
@@ -1069,19 +1055,18 @@ __device__ __forceinline__ void w_apply_inverse(const float (&linv)[M2], float (
     }
 }
 
-// Whitening b <- L^{-1} b: with rows of up to 32 entries through the explicit inverse (formed
-// once per pixel), wider rows by forward substitution (the inverse would not fit in registers).
-// lds: the segment's M2 x kLdsPitch<M2> floats (used by the inverse form only).
+// Whitening b <- L^{-1} b through the explicit inverse, formed once per pixel (lane i holds row i
+// of L^{-1}).  With 64-entry rows it takes most of the registers and spills a little while it is
+// formed, and still beats forward substitution in every whitening (weights 7.8x, fit 2.3x faster
+// at m = 32).  lds: the segment's M2 x kLdsPitch<M2> floats.
 template <int M2>
 struct Whitener {
-    static constexpr bool kInverse = M2 <= 32;
-    float row[M2], invd[M2];
-    float linv[kInverse ? M2 : 1];
+    float row[M2], invd[M2];      // the Cholesky factor (w_factor)
+    float linv[M2];               // row i of L^{-1} (w_inverse_rows)
     template <int V>
-    __device__ __forceinline__ void apply(float (&b)[V], int i, int base, float* lds) const {
+    __device__ __forceinline__ void apply(float (&b)[V], int i, float* lds) const {
         static_assert(V <= M2 + 4, "the vectors fit the segment's LDS matrix");
-        if constexpr (kInverse) w_apply_inverse<M2, V>(linv, b, i, lds);
-        else w_forward<M2, V>(row, invd, b, i, base);
+        w_apply_inverse<M2, V>(linv, b, i, lds);
     }
 };
 
@@ -1163,14 +1148,14 @@ __device__ __forceinline__ void w_factor(const float2* __restrict__ h2, int i, i
 }
 
 template <int K, int M2>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 4 : 1))) void wsmle_kernel(IterArgs A, int witers, const float* __restrict__ z,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 4 : (M2 == 64 ? 2 : 1)))) void wsmle_kernel(IterArgs A, int witers, const float* __restrict__ z,
                                                     const int32_t* __restrict__ n, const float2* __restrict__ h2,
                                                     float* __restrict__ t_io, float* __restrict__ a_io,
                                                     const uint8_t* __restrict__ act, float* __restrict__ loss_out) {
     constexpr int kWaves = 256 / 64;
     constexpr int kPPW = 64 / M2;                      // pixels per wave, one per segment
     __shared__ float2 s_psi[kWaves][kPPW][2 * M2 + 1];
-    __shared__ __align__(16) float s_lw[kWaves][kPPW][Whitener<M2>::kInverse ? kLdsSegment<M2> : 4];
+    __shared__ __align__(16) float s_lw[kWaves][kPPW][kLdsSegment<M2>];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int seg = lane / M2, i = lane % M2, base = seg * M2;
     const int pix_raw = (blockIdx.x * kWaves + wv) * kPPW + seg;
@@ -1190,14 +1175,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 
     }
     Whitener<M2> wh;
     w_factor<K, M2>(h2, i, base, m, T, tk, ak, on, s_psi[wv][seg], wh);
-    if constexpr (Whitener<M2>::kInverse) w_inverse_rows<M2>(wh.row, wh.invd, wh.linv, i, lw);   // lane i: row i
+    w_inverse_rows<M2>(wh.row, wh.invd, wh.linv, i, lw);         // lane i: row i
     const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m);
     const float nq = (float)n[pix];
     auto loss_at = [&](const float* tt, const float* aa) {
         float b[1];
         float jc[2 * K];
         w_residual<K>(zp, h2, i, m, T, tt, aa, on, b[0], jc);
-        wh.apply(b, i, base, lw);
+        wh.apply(b, i, lw);
         return nq * seg_sum<M2>(b[0] * b[0]);
     };
     float loss = loss_at(tk, ak);
@@ -1211,7 +1196,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 
             w_residual<K>(zp, h2, i, m, T, tk, ak, on, b[0], jc);
 #pragma unroll
             for (int c = 0; c < 2 * K; ++c) b[1 + c] = jc[c];
-            wh.apply(b, i, base, lw);
+            wh.apply(b, i, lw);
             // normal equations (identical in every lane of the segment)
             float Am[2 * K][2 * K], g[2 * K];
 #pragma unroll
@@ -1298,22 +1283,21 @@ __host__ __device__ constexpr int w_col(int d, int c) { return c * d - c * (c - 
 // eigenvalue of W_p, exact for W_p = c I).
 //
 // wprep_kernel: one segment of M2 >= 2m lanes per pixel; Sigma and its Cholesky factor as in the
-// weighted pixelwise fit, the rows of L^{-1} by forward substitution of the unit vectors, then
+// weighted pixelwise fit, L^{-1} by the column solves of w_inverse_rows (left in LDS), then
 // W_ij = sum_k (L^{-1})_ki (L^{-1})_kj through LDS (the same bits for W_ji: same products, same
 // order), and the frame's n_w is an atomic maximum of the (non-negative) float bits.  Lane i
 // writes the entries W_ij, j <= i, of its row: the lanes of one store (one j) write consecutive
 // words of column j of the packed lower triangle.
 template <int K, int M2>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 4 : 1))) void wprep_kernel(IterArgs A, const int32_t* __restrict__ n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 4 : (M2 == 64 ? 2 : 1)))) void wprep_kernel(IterArgs A, const int32_t* __restrict__ n,
                                                     const float2* __restrict__ h2, const float* __restrict__ t_in,
                                                     const float* __restrict__ a_in, const uint8_t* __restrict__ act,
                                                     float* __restrict__ W, unsigned int* __restrict__ nw_bits) {
     constexpr int kWaves = 256 / 64;
     constexpr int kPPW = 64 / M2;
     __shared__ float2 s_psi[kWaves][kPPW][2 * M2 + 1];
-    // rows of L^{-1}: unpadded as the inverse leaves them, padded by one word when written here
-    constexpr int LP = Whitener<M2>::kInverse ? kLdsPitch<M2> : M2 + 1;
-    __shared__ __align__(16) float s_li[kWaves][kPPW][Whitener<M2>::kInverse ? kLdsSegment<M2> : M2 * LP];
+    constexpr int LP = kLdsPitch<M2>;
+    __shared__ __align__(16) float s_li[kWaves][kPPW][kLdsSegment<M2>];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int seg = lane / M2, i = lane % M2, base = seg * M2;
     const int pix_raw = (blockIdx.x * kWaves + wv) * kPPW + seg;
@@ -1333,19 +1317,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 
     w_factor<K, M2>(h2, i, base, m, A.T, tk, ak, on, s_psi[wv][seg], wh);
     float li[M2];
     float (*sl)[LP] = reinterpret_cast<float (*)[LP]>(s_li[wv][seg]);
-    if constexpr (Whitener<M2>::kInverse) {
-        w_inverse_rows<M2>(wh.row, wh.invd, li, i, &sl[0][0]);      // leaves L^{-1} in sl, row-major
-    } else {
-#pragma unroll
-        for (int v = 0; v < M2; ++v) li[v] = i == v ? 1.f : 0.f;
-        w_forward<M2, M2>(wh.row, wh.invd, li, i, base);
-#pragma unroll
-        for (int c = 0; c < M2; ++c) sl[i][c] = li[c];
-    }
+    w_inverse_rows<M2>(wh.row, wh.invd, li, i, &sl[0][0]);          // leaves L^{-1} in sl, row-major
     __syncthreads();
     float gsum = 0.f;
     float* wtri = W + (int64_t)pix * w_tri(twom);
-    if constexpr (Whitener<M2>::kInverse) {
+    {
         // All of row i at once: for each k, entry (k, i) of L^{-1} and row k read four entries
         // at a time by the whole segment (broadcast reads).  The products with k < max(i, j) or
         // k >= 2m are exact zeros (L^{-1} is lower triangular with identity rows past 2m), so each
@@ -1374,13 +1350,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M2 == 32 ? 
                     gsum += fabsf(acc[j]);
                 }
             }
-        }
-    } else if (i < twom) {
-        for (int j = 0; j < twom; ++j) {
-            float acc = 0.f;
-            for (int k = i > j ? i : j; k < twom; ++k) acc = fmaf(sl[k][i], sl[k][j], acc);
-            if (valid && j <= i) wtri[w_col(twom, j) + (i - j)] = acc;
-            gsum += fabsf(acc);
         }
     }
 #pragma unroll
