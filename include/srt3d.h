@@ -394,12 +394,24 @@ int srt3d_weighted_iterate(srt3d_state* st, const float* d_z, const int32_t* d_n
  * srt3d_sketch_lanes: srt3d_sketch (eq. 3) with the number of lanes that share a pixel fixed
  *   to `lanes` (4, 8, 16, 32 or 64; anything else is SRT3D_EINVAL) instead of chosen from the
  *   mean photon count.  Same arguments, outputs and constraints as srt3d_sketch.
+ * srt3d_sketch_phases: the photon pass of srt3d_sketch (eq. 3) at 4 lanes per pixel (the
+ *   kernel srt3d_sketch_lanes runs with lanes = 4, so d_z and d_n come out identical to it),
+ *   which also writes the integer phase of every table entry it reads: for each photon p inside
+ *   some pixel's [offsets[i], offsets[i+1]) and each odd l <= m, d_k[(l-1) * N + p] =
+ *   (l * x) mod T, x being the stamp after folding into [0, T).  Even-l entries are not
+ *   written: that harmonic is the product of the l-1 entry and the l = 1 entry, so its phase
+ *   is their sum.  Entries of photons outside every pixel range are not written either.
+ *   d_k: int32 [m * N], device, caller-owned (null only when N = 0); other arguments as
+ *   srt3d_sketch without the accumulators and the error counters.
  * ------------------------------------------------------------------------------------- */
 int srt3d_phase_indices(const int32_t* d_x, int64_t N, int32_t T, int32_t m, int32_t* d_k,
                         void* stream);
 int srt3d_sketch_lanes(const int32_t* d_stamps, int64_t N, const int64_t* d_offsets, int32_t P,
                        int32_t T, int32_t m, const float* d_table, float* d_z, int32_t* d_n,
                        double* d_acc, int64_t* d_nacc, int32_t* d_err, int32_t lanes, void* stream);
+int srt3d_sketch_phases(const int32_t* d_stamps, int64_t N, const int64_t* d_offsets, int32_t P,
+                        int32_t T, int32_t m, const float* d_table, float* d_z, int32_t* d_n,
+                        int32_t* d_k, void* stream);
 
 const char* srt3d_strerror(int status);
 int srt3d_version(void);

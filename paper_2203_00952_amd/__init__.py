@@ -16,6 +16,7 @@ from ._lib import (  # noqa: F401
     events_workspace,
     hist_workspace,
     phase_indices,
+    sketch_phases,
     phase_table,
     sketch,
     sketch_events,

@@ -82,6 +82,7 @@ _SIGS = {
     "srt3d_reconstruct_noalloc": (_I32, [_VP, _VP, _VP, _I32, _I32, ctypes.POINTER(_Params), ctypes.POINTER(_State),
                                          _VP, _VP, _VP, _VP, _VP]),
     "srt3d_phase_indices": (_I32, [_VP, _I64, _I32, _I32, _VP, _VP]),
+    "srt3d_sketch_phases": (_I32, [_VP, _I64, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP]),
     "srt3d_strerror": (ctypes.c_char_p, [_I32]),
     "srt3d_version": (_I32, []),
 }
@@ -323,6 +324,26 @@ def phase_indices(x: torch.Tensor, T: int, m: int) -> torch.Tensor:
     _check(_lib().srt3d_phase_indices(_dev(x, torch.int32, "x"), x.numel(), T, m, _ptr(k), _stream(x.device)),
            "srt3d_phase_indices")
     return k
+
+
+def sketch_phases(stamps: torch.Tensor, offsets: torch.Tensor, T: int, m: int):
+    """The photon pass at 4 lanes per pixel with the phase of every table read written out
+    (srt3d_sketch_phases).  Returns (z, n, k int32 [m, N]); rows of even l, and photons outside
+    every pixel range, hold -1."""
+    if offsets.dim() != 1 or offsets.numel() < 2:
+        raise ValueError("offsets must be [P + 1] with P >= 1")
+    P = offsets.numel() - 1
+    dev = offsets.device
+    N = stamps.numel()
+    z, n = _sketch_outputs(P, m, dev, None, None, None, None, None)
+    if not (2 <= T and T * 8 <= 65536):
+        raise ValueError("sketch_phases: invalid T")
+    table = cached_phase_table(T, dev)
+    k = torch.full((m, N), -1, dtype=torch.int32, device=dev)
+    _check(_lib().srt3d_sketch_phases(_dev(stamps, torch.int32, "stamps"), N, _dev(offsets, torch.int64, "offsets"), P,
+                                      T, m, _dev(table, torch.float32, "table"), _dev(z, torch.float32, "z"),
+                                      _dev(n, torch.int32, "n"), _ptr(k), _stream(dev)), "srt3d_sketch_phases")
+    return z, n, k
 
 
 # ----------------------------------------------------------------------------- reconstruction

@@ -472,6 +472,16 @@ int srt3d_phase_indices(const int32_t* d_x, int64_t N, int32_t T, int32_t m, int
     return dev_status(launch_phase_indices(d_x, N, T, m, d_k, as_stream(stream)));
 }
 
+int srt3d_sketch_phases(const int32_t* d_stamps, int64_t N, const int64_t* d_offsets, int32_t P, int32_t T, int32_t m,
+                        const float* d_table, float* d_z, int32_t* d_n, int32_t* d_k, void* stream) {
+    if (P < 1 || N < 0 || !sketch_dims_ok(T, m)) return SRT3D_EINVAL;
+    if ((!d_stamps && N > 0) || (!d_k && N > 0) || !d_offsets || !d_table || !d_z || !d_n) return SRT3D_EINVAL;
+    if (!aligned(d_table, 8) || !aligned(d_z, 8)) return SRT3D_EINVAL;
+    return dev_status(launch_sketch_photons_export(d_stamps, N, d_offsets, P, T, m,
+                                                   reinterpret_cast<const float2*>(d_table), d_z, d_n, d_k,
+                                                   as_stream(stream)));
+}
+
 int srt3d_phase_table(int32_t T, float* d_table, void* stream) {
     if (T < 2 || (int64_t)T * 8 > 65536 || !d_table || !aligned(d_table, 8)) return SRT3D_EINVAL;
     return dev_status(launch_phase_table(T, reinterpret_cast<float2*>(d_table), as_stream(stream)));

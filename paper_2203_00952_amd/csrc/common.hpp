@@ -82,6 +82,10 @@ hipError_t launch_phase_indices(const int32_t* x, int64_t N, int T, int m, int32
 hipError_t launch_sketch_photons(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T,
                                  int m, const float2* table, float* z, int32_t* n, double* acc,
                                  int64_t* nacc, int32_t* err, hipStream_t s, int lanes = 0);
+// the photon pass (four lanes per pixel) also writing the table index of every harmonic it reads
+// from the table: kexp[(l - 1) N + p]
+hipError_t launch_sketch_photons_export(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T, int m,
+                                        const float2* table, float* z, int32_t* n, int32_t* kexp, hipStream_t s);
 hipError_t launch_sketch_binned(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T,
                                 int m, const float2* table, float* z, int32_t* n, double* acc,
                                 int64_t* nacc, int32_t* err, hipStream_t s);

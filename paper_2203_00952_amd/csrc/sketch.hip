@@ -76,9 +76,11 @@ __device__ __forceinline__ void reduce_scatter(float* v, int lane, int& base) {
 }
 
 // Add photon x's harmonics l0+1 .. l0+MC into v (odd ones from the table, even ones as the
-// preceding entry times exp(i w_1 x)).
-template <int MC, bool POW2>
-__device__ __forceinline__ void add_photon(float* v, int32_t x, int l0, int T, uint32_t T8, const char* tab) {
+// preceding entry times exp(i w_1 x)).  EXPORT (inspection only): also write the table index of
+// every harmonic read from the table, kexp[(l - 1) N + pidx]; the others are left as they are.
+template <int MC, bool POW2, bool EXPORT>
+__device__ __forceinline__ void add_photon(float* v, int32_t x, int l0, int T, uint32_t T8, const char* tab,
+                                           int32_t* kexp, int64_t N, int64_t pidx) {
     const uint32_t x8 = (uint32_t)x << 3;
     if constexpr (MC == 1) {
         uint32_t k8 = x8;
@@ -87,6 +89,7 @@ __device__ __forceinline__ void add_photon(float* v, int32_t x, int l0, int T, u
             k8 = (POW2 ? (lx & (uint32_t)(T - 1)) : (lx % (uint32_t)T)) << 3;
         }
         const float2 c = *reinterpret_cast<const float2*>(tab + k8);
+        if constexpr (EXPORT) kexp[(int64_t)l0 * N + pidx] = (int32_t)(k8 >> 3);
         v[0] += c.x;
         v[1] += c.y;
     } else {
@@ -100,6 +103,7 @@ __device__ __forceinline__ void add_photon(float* v, int32_t x, int l0, int T, u
 #pragma unroll
         for (int j = 0; j < MC; j += 2) {
             const float2 c = (j == 0 && l0 == 0) ? u1 : *reinterpret_cast<const float2*>(tab + k8);
+            if constexpr (EXPORT) kexp[(int64_t)(l0 + j) * N + pidx] = (int32_t)(((j == 0 && l0 == 0) ? x8 : k8) >> 3);
             v[2 * j] += c.x;
             v[2 * j + 1] += c.y;
             // next harmonic: += c * u1, as four fused multiply-adds
@@ -126,11 +130,11 @@ __device__ __forceinline__ void add_photon(float* v, int32_t x, int l0, int T, u
 constexpr int kU = 4;
 constexpr int kSeg = 32;
 
-template <int MC, int G, bool POW2>
+template <int MC, int G, bool POW2, bool EXPORT>
 __device__ __forceinline__ void sketch_pass(const int32_t* __restrict__ stamps, int64_t b, int64_t e, int lane,
                                             int l0, int T, uint32_t T8, const float2* s_table, int64_t count,
                                             int64_t count_total, float* __restrict__ zrow,
-                                            double* __restrict__ accrow, int& bad) {
+                                            double* __restrict__ accrow, int& bad, int32_t* kexp, int64_t N) {
     constexpr int V = 2 * MC;
     constexpr int KEEP = V >= G ? V / G : 1;
     constexpr int DUP = V >= G ? 1 : G / V;       // lanes holding identical sums
@@ -159,7 +163,7 @@ __device__ __forceinline__ void sketch_pass(const int32_t* __restrict__ stamps, 
                     x = fold_stamp(x, T);
                     if (l0 == 0) ++bad;
                 }
-                add_photon<MC, POW2>(v, x, l0, T, T8, tab);
+                add_photon<MC, POW2, EXPORT>(v, x, l0, T, T8, tab, kexp, N, p + u * G);
             }
         }
 #pragma unroll
@@ -198,11 +202,11 @@ __device__ __forceinline__ void sketch_pass(const int32_t* __restrict__ stamps, 
 // known at compile time, so the byte phase k8 is the ds_read address with no base add.
 // MCMAX bounds the harmonics per pass (16 or 32): the register budget, and with it occupancy,
 // follows the largest pass the kernel contains, so m <= 16 uses a kernel without the 32 pass.
-template <int G, bool POW2, int TB, int MCMAX>
+template <int G, bool POW2, int TB, int MCMAX, bool EXPORT>
 __global__ __launch_bounds__(256) void sketch_photons_kernel(
     const int32_t* __restrict__ stamps, int64_t N, const int64_t* __restrict__ offsets, int P, int T, int m,
     const float2* __restrict__ table, float* __restrict__ z, int32_t* __restrict__ nout,
-    double* __restrict__ acc, int64_t* __restrict__ nacc, int32_t* __restrict__ err) {
+    double* __restrict__ acc, int64_t* __restrict__ nacc, int32_t* __restrict__ err, int32_t* __restrict__ kexp) {
     __shared__ float2 s_table[TB];
     for (int i = threadIdx.x; i < T; i += blockDim.x) s_table[i] = table[i];
     __syncthreads();
@@ -237,13 +241,13 @@ __global__ __launch_bounds__(256) void sketch_photons_kernel(
             switch (mc) {
                 case 32:
                     if constexpr (MCMAX >= 32)
-                        sketch_pass<32, G, POW2>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps);
+                        sketch_pass<32, G, POW2, EXPORT>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps, kexp, N);
                     break;
-                case 16: sketch_pass<16, G, POW2>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps); break;
-                case 8: sketch_pass<8, G, POW2>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps); break;
-                case 4: sketch_pass<4, G, POW2>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps); break;
-                case 2: sketch_pass<2, G, POW2>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps); break;
-                default: sketch_pass<1, G, POW2>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps); break;
+                case 16: sketch_pass<16, G, POW2, EXPORT>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps, kexp, N); break;
+                case 8: sketch_pass<8, G, POW2, EXPORT>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps, kexp, N); break;
+                case 4: sketch_pass<4, G, POW2, EXPORT>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps, kexp, N); break;
+                case 2: sketch_pass<2, G, POW2, EXPORT>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps, kexp, N); break;
+                default: sketch_pass<1, G, POW2, EXPORT>(stamps, b, e, lane, l0, T, T8, s_table, count, count_total, zrow, accrow, bad_stamps, kexp, N); break;
             }
             l0 += mc;
         }
@@ -258,22 +262,22 @@ __global__ __launch_bounds__(256) void sketch_photons_kernel(
     }
 }
 
-template <int G, bool POW2, int TB, int MCMAX>
+template <int G, bool POW2, int TB, int MCMAX, bool EXPORT = false>
 static hipError_t launch_sketch_g(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T, int m,
                                   const float2* table, float* z, int32_t* n, double* acc, int64_t* nacc,
-                                  int32_t* err, hipStream_t s) {
+                                  int32_t* err, hipStream_t s, int32_t* kexp = nullptr) {
     constexpr int threads = 256;
     int cus = 0, per_cu = 0;
     hipError_t st = current_device_cus(&cus);
     if (st != hipSuccess) return st;
-    st = cached_occupancy<sketch_photons_kernel<G, POW2, TB, MCMAX>, threads>(&per_cu);
+    st = cached_occupancy<sketch_photons_kernel<G, POW2, TB, MCMAX, EXPORT>, threads>(&per_cu);
     if (st != hipSuccess) return st;
     const int64_t groups_per_block = threads / G;
     const int64_t need = ((int64_t)P + groups_per_block - 1) / groups_per_block;
     const int64_t cap = (int64_t)cus * per_cu;
     const unsigned blocks = (unsigned)(need < cap ? need : cap);
-    hipLaunchKernelGGL((sketch_photons_kernel<G, POW2, TB, MCMAX>), dim3(blocks), dim3(threads), 0, s, stamps, N, offsets,
-                       P, T, m, table, z, n, acc, nacc, err);
+    hipLaunchKernelGGL((sketch_photons_kernel<G, POW2, TB, MCMAX, EXPORT>), dim3(blocks), dim3(threads), 0, s, stamps, N,
+                       offsets, P, T, m, table, z, n, acc, nacc, err, kexp);
     return hipGetLastError();
 }
 
@@ -289,6 +293,30 @@ static hipError_t launch_sketch_tb(const int32_t* stamps, int64_t N, const int64
     if (T <= 4096) SRT3D_TB(4096);
     SRT3D_TB(8192);
 #undef SRT3D_TB
+}
+
+// The photon pass with its table indices written out (inspection): four lanes per pixel (the
+// lane count decides which lane takes a photon, not how its phases are formed), otherwise the
+// kernel and pass structure of launch_sketch_photons for this T and m.
+template <bool POW2>
+static hipError_t launch_sketch_export_tb(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T, int m,
+                                          const float2* table, float* z, int32_t* n, int32_t* kexp, hipStream_t s) {
+#define SRT3D_TBX(TBV)                                                                                                    \
+    return m <= 16 ? launch_sketch_g<4, POW2, TBV, 16, true>(stamps, N, offsets, P, T, m, table, z, n, nullptr, nullptr, \
+                                                             nullptr, s, kexp)                                          \
+                   : launch_sketch_g<4, POW2, TBV, 32, true>(stamps, N, offsets, P, T, m, table, z, n, nullptr, nullptr, \
+                                                             nullptr, s, kexp)
+    if (T <= 1024) SRT3D_TBX(1024);
+    if (T <= 2048) SRT3D_TBX(2048);
+    if (T <= 4096) SRT3D_TBX(4096);
+    SRT3D_TBX(8192);
+#undef SRT3D_TBX
+}
+
+hipError_t launch_sketch_photons_export(const int32_t* stamps, int64_t N, const int64_t* offsets, int P, int T, int m,
+                                        const float2* table, float* z, int32_t* n, int32_t* kexp, hipStream_t s) {
+    return (T & (T - 1)) == 0 ? launch_sketch_export_tb<true>(stamps, N, offsets, P, T, m, table, z, n, kexp, s)
+                              : launch_sketch_export_tb<false>(stamps, N, offsets, P, T, m, table, z, n, kexp, s);
 }
 
 // Lanes per pixel from the mean photon count: enough lanes to keep the stride loop busy, few

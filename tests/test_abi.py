@@ -171,6 +171,11 @@ def test_invalid_arguments_rejected_on_host(lib):
                                       None) == -1
     assert lib.srt3d_sketch_lanes(fake, 10, fake, 4, 1024, 513, fake, fake, fake, None, None, None, 16, None) == -1
     assert lib.srt3d_sketch_lanes(fake, 10, fake, 4, 1024, 4, fake, None, fake, None, None, None, 16, None) == -1
+    # phase export: the sketch's checks plus a NULL index buffer with photons
+    assert lib.srt3d_sketch_phases(fake, 10, fake, 4, 1024, 4, fake, fake, fake, None, None) == -1
+    assert lib.srt3d_sketch_phases(fake, 10, fake, 4, 1024, 513, fake, fake, fake, fake, None) == -1
+    assert lib.srt3d_sketch_phases(fake, 10, fake, 0, 1024, 4, fake, fake, fake, fake, None) == -1
+    assert lib.srt3d_sketch_phases(fake, 10, fake, 4, 1024, 4, fake, VP(0x1004), fake, fake, None) == -1
     # event streams: P < 1, m > T/2, NULL pixels with events, NULL workspace, misaligned or too
     # small workspace, N or P past the limits
     ws = VP(0x10000)

@@ -44,6 +44,42 @@ def test_phase_indices_bit_exact():
         np.testing.assert_array_equal(k, OS.phase_indices(x, T, m))
 
 
+@pytest.mark.parametrize("T,m", [(4096, 16), (4613, 5), (1024, 33), (8192, 64), (2048, 1), (7, 3), (3000, 31)])
+def test_photon_pass_phases_bit_exact(T, m):
+    """The phases the photon pass itself reads from its table (eq. 3's exact integer part):
+    every odd harmonic's index equals (l x) mod T after folding; even harmonics are formed as
+    the product of the l-1 and l = 1 entries and read nothing.  The pass that writes them is
+    the 4-lane production kernel, so its z and n must equal srt3d_sketch_lanes' bit for bit."""
+    dev = device()
+    rng = np.random.default_rng(T * 17 + m)
+    counts = rng.integers(0, 120, 301)
+    counts[::13] = 0
+    counts[7] = 2000
+    skip = 37                                      # leading photons that belong to no pixel
+    N = skip + int(counts.sum()) + 11              # and a trailing run
+    x = rng.integers(0, T, N)
+    wild = rng.random(N) < 0.05                    # out-of-range stamps, folded into [0, T)
+    x[wild] = rng.integers(-3 * T, 4 * T, int(wild.sum()))
+    offsets = np.concatenate([[0], np.cumsum(counts)]) + skip
+    covered = np.zeros(N, bool)
+    covered[skip:skip + int(counts.sum())] = True
+    st = torch.from_numpy(x.astype(np.int32)).to(dev)
+    off = torch.from_numpy(offsets.astype(np.int64)).to(dev)
+    _print_case(test="pass_phases", T=T, m=m, N=N)
+    z, n, k = srt.sketch_phases(st, off, T, m)
+    z4, n4 = srt.sketch(st, off, T, m, lanes=4)
+    torch.cuda.synchronize()
+    k = k.cpu().numpy()
+    ref = OS.phase_indices(x, T, m)
+    odd = np.arange(m) % 2 == 0                    # rows l-1 of odd l
+    np.testing.assert_array_equal(k[np.ix_(odd, covered)], ref[np.ix_(odd, covered)])
+    assert np.all(k[~odd] == -1) and np.all(k[:, ~covered] == -1)
+    for l in range(2, m + 1, 2):                   # phase of the product = sum of the phases
+        np.testing.assert_array_equal((k[l - 2, covered] + k[0, covered]) % T, ref[l - 1, covered])
+    assert torch.equal(z, z4) and torch.equal(n, n4)
+    assert np.count_nonzero(wild & covered) > 0
+
+
 def _check_sketch(stamps_np, offsets_np, T, m, z, n, label):
     zr, nr = OS.sketch(stamps_np, offsets_np, T, m)
     np.testing.assert_array_equal(n.cpu().numpy(), nr)
