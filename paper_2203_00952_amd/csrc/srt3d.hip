@@ -30,6 +30,7 @@ constexpr int kInitBlocksMax = 4096; // init workgroups at most; also the number
 struct IterArgs {
     int rows, cols, P, T, m, K, R, Rb;
     float lambda_z, r_min;
+    float invT, twoinvT;    // 1 / T and 2 / T, correctly rounded (host division)
 };
 
 // ----------------------------------------------------------------------------- helpers
@@ -572,20 +573,21 @@ __device__ __forceinline__ void residual_pass(const Src& src, int lo, int hi, in
 // One data step for the K points of a pixel, by the four lanes `sub` = 0..3 of the pixel; each
 // lane's slice of harmonics has at most MS entries.
 template <int K, int MS, class Src>
-__device__ __forceinline__ void data_point(const Src& src, int sub, int m, int T, float nn, float gam_t, float gam_a,
-                                           float* tk, float* ak, const bool* on) {
+__device__ __forceinline__ void data_point(const Src& src, int sub, int m, int T, float invT, float twoinvT, float nn,
+                                           float gam_t, float gam_a, float* tk, float* ak, const bool* on) {
     const int lo = (sub * m) / kLanesPerPixel, hi = ((sub + 1) * m) / kLanesPerPixel;
-    const float Tf = (float)T, invT = 1.0f / Tf, twoinvT = 2.0f / Tf;
+    const float Tf = (float)T;
+    // sums start at -0 (x + -0 = x exactly, so the first add is dropped)
     float gt[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) gt[k] = 0.f;
+    for (int k = 0; k < K; ++k) gt[k] = -0.f;
     residual_pass<K, MS>(src, lo, hi, T, invT, twoinvT, tk, ak, on, gt, true);
 #pragma unroll
     for (int k = 0; k < K; ++k)
         if (on[k]) tk[k] = wrap_t(tk[k] - gam_t * (-2.f * nn * ak[k] * gt[k]), Tf);
     float ga[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) ga[k] = 0.f;
+    for (int k = 0; k < K; ++k) ga[k] = -0.f;
     residual_pass<K, MS>(src, lo, hi, T, invT, twoinvT, tk, ak, on, ga, false);
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -616,7 +618,7 @@ __global__ __launch_bounds__(256) void data_step_kernel(IterArgs A, const float*
     if (!any) return;
     const GlobalSketch src{reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * A.m),
                            reinterpret_cast<const float2*>(hhat)};
-    data_point<K, kMaxSlice>(src, sub, A.m, A.T, (float)n[pix], scal[1], scal[2], tk, ak, on);
+    data_point<K, kMaxSlice>(src, sub, A.m, A.T, A.invT, A.twoinvT, (float)n[pix], scal[1], scal[2], tk, ak, on);
     if (sub != 0) return;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -719,7 +721,8 @@ __device__ __forceinline__ void smle_pixel(const Src& src, int pix, int sub, con
 #pragma unroll
         for (int k = 0; k < K; ++k) any |= on[k];
         if (any)
-            for (int it = 0; it < iters; ++it) data_point<K, MS>(src, sub, A.m, A.T, nstep, scal[1], scal[2], tk, ak, on);
+            for (int it = 0; it < iters; ++it)
+                data_point<K, MS>(src, sub, A.m, A.T, A.invT, A.twoinvT, nstep, scal[1], scal[2], tk, ak, on);
         const float L = nq * smle_residual<K, MS>(src, lo, hi, A.T, tk, ak, on);
         if (s == 0 || L < best) {
             best = L;
@@ -1536,11 +1539,12 @@ __device__ constexpr float full_moment(int r, int c) {
 template <int K, int R>
 __device__ __forceinline__ void dd_start(float (&M)[4][4], float (&b)[4], bool first) {
     constexpr bool SUB = (K == 1) && (R <= 2);
+    // zero sums start at -0, the identity of addition, so the first update is a plain product
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        b[r] = 0.f;
+        b[r] = -0.f;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) M[r][c] = (SUB && first) ? full_moment<R>(r, c) : 0.f;
+        for (int c = 0; c < 4; ++c) M[r][c] = (SUB && first) ? full_moment<R>(r, c) : -0.f;
     }
 }
 
@@ -1555,7 +1559,7 @@ __device__ __forceinline__ void dd_rows(const float* st, const uint8_t* sa, int 
             const float q = win_q<R>(di, dj);
             const int r2 = di * di + dj * dj;
             // the cell's gated offsets: their sum and how many pass (or, with SUB, fail) the gate
-            float dsum = 0.f, cnt = 0.f;
+            float dsum = -0.f, cnt = -0.f;
 #pragma unroll
             for (int kk = 0; kk < K; ++kk) {
                 const int cn = ((ci + di) * E + (cj + dj)) * K + kk;
@@ -1564,19 +1568,19 @@ __device__ __forceinline__ void dd_rows(const float* st, const uint8_t* sa, int 
                 dsum += gate ? d : 0.f;
                 cnt += (SUB ? !gate : gate) ? 1.f : 0.f;
             }
-            const float qd = q * dsum;
-            b[0] += qd;
-            if (di != 0) b[1] += (float)di * qd;
-            if (dj != 0) b[2] += (float)dj * qd;
-            if (r2 != 0) b[3] += (float)r2 * qd;
-            const float sq = (SUB ? -q : q) * cnt;
-            M[0][0] += sq;
-            if (di != 0) { M[0][1] += sq * di; M[1][1] += sq * (di * di); }
-            if (dj != 0) { M[0][2] += sq * dj; M[2][2] += sq * (dj * dj); }
-            if (di != 0 && dj != 0) M[1][2] += sq * (di * dj);
-            if (r2 != 0) { M[0][3] += sq * r2; M[3][3] += sq * (r2 * r2); }
-            if (di != 0 && r2 != 0) M[1][3] += sq * (di * r2);
-            if (dj != 0 && r2 != 0) M[2][3] += sq * (dj * r2);
+            // q phi_r is an integer below 2^24 for R <= 2, so each update is one fused multiply-add
+            b[0] = fmaf(q, dsum, b[0]);
+            if (di != 0) b[1] = fmaf(q * (float)di, dsum, b[1]);
+            if (dj != 0) b[2] = fmaf(q * (float)dj, dsum, b[2]);
+            if (r2 != 0) b[3] = fmaf(q * (float)r2, dsum, b[3]);
+            const float sq = SUB ? -q : q;
+            M[0][0] = fmaf(sq, cnt, M[0][0]);
+            if (di != 0) { M[0][1] = fmaf(sq * di, cnt, M[0][1]); M[1][1] = fmaf(sq * (di * di), cnt, M[1][1]); }
+            if (dj != 0) { M[0][2] = fmaf(sq * dj, cnt, M[0][2]); M[2][2] = fmaf(sq * (dj * dj), cnt, M[2][2]); }
+            if (di != 0 && dj != 0) M[1][2] = fmaf(sq * (di * dj), cnt, M[1][2]);
+            if (r2 != 0) { M[0][3] = fmaf(sq * r2, cnt, M[0][3]); M[3][3] = fmaf(sq * (r2 * r2), cnt, M[3][3]); }
+            if (di != 0 && r2 != 0) M[1][3] = fmaf(sq * (di * r2), cnt, M[1][3]);
+            if (dj != 0 && r2 != 0) M[2][3] = fmaf(sq * (dj * r2), cnt, M[2][3]);
         }
     }
 }
@@ -1643,8 +1647,8 @@ __device__ __forceinline__ void id_part(const float* st, const uint8_t* sa, cons
                                         int k, float Tf, float invT, float tau_z, int s, float& num, float& den) {
     constexpr int W = 2 * R + 1;
     const float tq = st[(ci * E + cj) * K + k];
-    num = 0.f;
-    den = 0.f;
+    num = -0.f;
+    den = -0.f;
 #pragma unroll
     for (int jj = 0; jj < (W * W + kIdParts - 1) / kIdParts; ++jj) {
         const int w = s + kIdParts * jj;
@@ -1752,7 +1756,7 @@ __global__ __launch_bounds__(kTile * kTile) void depth_denoise_kernel(
         const int c = ((ti + R) * E + (tj + R)) * K + k;
         a_out[q] = a_in[q];
         act_out[q] = s_a[c];
-        t_out[q] = s_a[c] ? dd_point<K, R>(s_t, s_a, E, ti + R, tj + R, k, Tf, 1.0f / Tf, tau_z, A.lambda_z) : s_t[c];
+        t_out[q] = s_a[c] ? dd_point<K, R>(s_t, s_a, E, ti + R, tj + R, k, Tf, A.invT, tau_z, A.lambda_z) : s_t[c];
     }
 }
 
@@ -1779,7 +1783,7 @@ __global__ __launch_bounds__(kTile * kTile) void intensity_denoise_kernel(
     for (int k = 0; k < K; ++k) {
         const int c = ((ti + R) * E + (tj + R)) * K + k;
         was[k] = s_a[c] != 0;
-        rt[k] = was[k] ? id_mean<K, R>(s_t, s_a, s_r, E, ti + R, tj + R, k, Tf, 1.0f / Tf, tau_z) : 0.f;
+        rt[k] = was[k] ? id_mean<K, R>(s_t, s_a, s_r, E, ti + R, tj + R, k, Tf, A.invT, tau_z) : 0.f;
         t_out[(int64_t)pix * K + k] = s_t[c];
     }
     id_update<K>(rt, was, (float)n[pix], A.r_min, an, keep);
@@ -1803,6 +1807,7 @@ __global__ __launch_bounds__(kTile * kTile) void intensity_denoise_kernel(
 // iteration and the ring makes each tile fit 1.9 times its own pixels; the separate launch fits
 // each pixel once.  dd_point sees the same inputs either way, so both forms give the same bits.
 constexpr int kIterTY = 8, kIterTX = 16;
+constexpr int kRsrcFlags = 0x00020000;   // buffer descriptor word 3: raw 32-bit dwords
 
 constexpr int kIterPix = kIterTY * kIterTX;
 constexpr int kIterThreads = kIterPix * kLanesPerPixel;
@@ -1836,10 +1841,22 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
     float2 zr[kPrefetchSlice];
     if constexpr (DS_NEXT) {
         if (prefetch) {
-            const int lo = (sub * A.m) / kLanesPerPixel, hi = ((sub + 1) * A.m) / kLanesPerPixel;
-            const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)dpix * 2 * A.m);
+            // A wave is one tile row of 16 pixels (kIterTX * kLanesPerPixel = 64 lanes).  Its
+            // sketch rows are read through a buffer descriptor that starts at the wave's first
+            // pixel and ends at the end of z: each lane reads kPrefetchSlice entries from the
+            // start of its slice at constant offsets, and reads past the end of z (pixels right
+            // of the frame, the frame's last slice) return 0.  Entries beyond the slice are not used.
+            static_assert(kIterTX * kLanesPerPixel == kWave, "one tile row per wave");
+            const int lo = (sub * A.m) / kLanesPerPixel;
+            const int64_t p0 = (int64_t)__builtin_amdgcn_readfirstlane(dpi) * A.cols + j0;
+            const int64_t left = p0 < A.P ? ((int64_t)A.P - p0) * A.m * 8 : 0;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float*>(z) + (p0 < A.P ? p0 : 0) * 2 * A.m, (short)0,
+                (int)(left < 0x7fffffff ? left : 0x7fffffff), kRsrcFlags);
+            const int voff = (dtj * A.m + lo) * 8;
 #pragma unroll
-            for (int j = 0; j < kPrefetchSlice; ++j) zr[j] = zp[lo + j < hi ? lo + j : lo];
+            for (int j = 0; j < kPrefetchSlice; ++j)
+                zr[j] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, j * 8, 0));
         }
     }
     if constexpr (DS_NEXT)
@@ -1848,11 +1865,13 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
         load_region<K, false>(s_t2, s_a2, nullptr, E2Y, E2, i0 - 2 * R, j0 - 2 * R, A, t_in, a_in, act_in, nullptr);
     load_region<K, true>(s_td, s_a1, s_r1, E1Y, E1, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
     lds_barrier();
-    const float Tf = (float)A.T, invT = 1.0f / Tf, tau_z = scal[3];
+    const float Tf = (float)A.T, invT = A.invT, tau_z = scal[3];
     constexpr bool SPLIT_DD = !DD_DONE && K == 1 && E1Y * E1 <= kIterThreads / 2;
     if constexpr (SPLIT_DD) {
         // depth denoiser on the tile + R ring, one cell per thread of each half of the block:
-        // waves 0-3 sum window rows -R..0, waves 4-7 rows 1..R and pass theirs on through LDS
+        // waves 0-3 sum window rows -R..0 and pass theirs on through LDS, waves 4-7 sum rows
+        // 1..R, add part 0 (the sum is the same either way round) and solve -- the larger part
+        // on one side, the solve on the other
         const bool second = threadIdx.x >= kIterThreads / 2;            // uniform per wave
         const int idx = threadIdx.x - (second ? kIterThreads / 2 : 0);
         float M[4][4], b[4];
@@ -1867,14 +1886,14 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
                 dd_start<K, R>(M, b, !second);
                 if (second) {
                     dd_rows<K, R, 1, R>(s_t2, s_a2, E2, ci, cj, tq, Tf, invT, tau_z, M, b);
-                    dd_pack(M, b, s_ddp + idx * kDDPart);
                 } else {
                     dd_rows<K, R, -R, 0>(s_t2, s_a2, E2, ci, cj, tq, Tf, invT, tau_z, M, b);
+                    dd_pack(M, b, s_ddp + idx * kDDPart);
                 }
             }
         }
         lds_barrier();
-        if (!second && idx < E1Y * E1) {
+        if (second && idx < E1Y * E1) {
             if (fit) {
                 dd_add_part(M, b, s_ddp + idx * kDDPart);
                 s_td[idx] = dd_solve(M, b, tq, Tf, A.lambda_z);
@@ -1924,10 +1943,11 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
             if (any) {
                 if (prefetch) {
                     const RegSketch<kPrefetchSlice> src{zr, s_h};
-                    data_point<K, kPrefetchSlice>(src, sub, A.m, A.T, nq, scal[1], scal[2], tk, ak, on);
+                    data_point<K, kPrefetchSlice>(src, sub, A.m, A.T, A.invT, A.twoinvT, nq, scal[1], scal[2], tk, ak,
+                                                  on);
                 } else {
                     const GlobalSketch src{reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * A.m), s_h};
-                    data_point<K, kMaxSlice>(src, sub, A.m, A.T, nq, scal[1], scal[2], tk, ak, on);
+                    data_point<K, kMaxSlice>(src, sub, A.m, A.T, A.invT, A.twoinvT, nq, scal[1], scal[2], tk, ak, on);
                 }
             }
         }
@@ -2015,6 +2035,8 @@ static IterArgs make_args(const srt3d_params& p) {
     A.Rb = p.Rb;
     A.lambda_z = p.lambda_z;
     A.r_min = p.r_min;
+    A.invT = 1.0f / (float)p.T;
+    A.twoinvT = 2.0f / (float)p.T;
     return A;
 }
 
