@@ -295,7 +295,22 @@ __device__ __forceinline__ void step_sizes_store(int nmax_i, int K, float eta_t,
 // RHO: the first pick's correlation stays in LDS (NT <= KSMAX column tiles, 16 bytes per lane and
 // tile) and the later picks update it with rho; otherwise every pick recomputes it from the
 // updated working sketch.
-template <int K, int KSMAX, bool RHO>
+// Argmax step across lanes: take the partner's entry if its value is larger, or equal with a
+// smaller grid index (a total order, so any pairing sequence gives the same winner).
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(float& best, int& bestg) {
+    const float ob = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, best), CTRL, 0xf, 0xf,
+                                                                       false));
+    const int og = __builtin_amdgcn_mov_dpp(bestg, CTRL, 0xf, 0xf, false);
+    if (ob > best || (ob == best && og < bestg)) {
+        best = ob;
+        bestg = og;
+    }
+}
+
+// EBL: the grid table is first copied to LDS (dynamic shared memory of NT KS 64 floats), so
+// the B operands of every column tile are LDS reads instead of L2 round trips.
+template <int K, int KSMAX, bool RHO, bool EBL>
 __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, const int32_t* __restrict__ n,
                                                    const float* __restrict__ hhat, float* __restrict__ scal,
                                                    const float* __restrict__ EB, const float* __restrict__ rho, int P,
@@ -306,10 +321,20 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
                                                    float eta_a) {
     __shared__ float s_rho[RHO ? 16 * KSMAX : 1];
     __shared__ v4f s_C[RHO ? 4 * KSMAX * 64 : 1];     // [wave][column tile][lane]
+    extern __shared__ float s_eb[];                   // EBL: the grid table
     if constexpr (RHO) {
         for (int i = threadIdx.x; i < 16 * KSMAX; i += blockDim.x) s_rho[i] = i < 16 * NT ? rho[i] : 0.f;
         __syncthreads();
     }
+    if constexpr (EBL) {
+        for (int i = threadIdx.x; i < NT * KS * 64; i += blockDim.x) s_eb[i] = EB[i];
+        __syncthreads();
+    }
+    // B fragment ks of column tile nt for this lane
+    auto ebv = [&](int nt, int ks, int lane_) -> float {
+        if constexpr (EBL) return s_eb[(nt * KS + ks) * 64 + lane_];
+        else return EB[(int64_t)(nt * KS + ks) * 64 + lane_];
+    };
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r = lane & 15, kq = lane >> 4;          // A row (pixel) / k quarter of this lane
     const float e2 = scal[4], invT = 1.0f / (float)T, twoinvT = 2.0f / (float)T;
@@ -389,15 +414,14 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
                 }
             } else {
                 for (int nt = 0; nt < NT; nt += 2) {
-                    const float* eb0 = EB + (int64_t)nt * KS * 64 + lane;
                     v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
                     if (nt + 1 < NT) {
-                        const float* eb1 = eb0 + KS * 64;
 #pragma unroll
                         for (int ks = 0; ks < KSMAX; ++ks)
                             if (ks < KS) {
-                                acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[ks], eb0[ks * 64], acc0, 0, 0, 0);
-                                acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[ks], eb1[ks * 64], acc1, 0, 0, 0);
+                                acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[ks], ebv(nt, ks, lane), acc0, 0, 0, 0);
+                                acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[ks], ebv(nt + 1, ks, lane), acc1, 0, 0,
+                                                                            0);
                             }
                         scan(acc0, nt);
                         scan(acc1, nt + 1);
@@ -408,23 +432,20 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
                     } else {
 #pragma unroll
                         for (int ks = 0; ks < KSMAX; ++ks)
-                            if (ks < KS) acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[ks], eb0[ks * 64], acc0, 0, 0, 0);
+                            if (ks < KS) acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[ks], ebv(nt, ks, lane), acc0, 0, 0, 0);
                         scan(acc0, nt);
                         if (RHO) Cw[64 * nt] = acc0;
                     }
                 }
             }
+            // argmax over the 16 lanes of each row (DPP: pairs within quads, then the two quads of
+            // each half row, then the two half rows)
 #pragma unroll
-            for (int o = 1; o < 16; o <<= 1) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float ob = __shfl_xor(best[i], o, 64);
-                    const int og = __shfl_xor(bestg[i], o, 64);
-                    if (ob > best[i] || (ob == best[i] && og < bestg[i])) {
-                        best[i] = ob;
-                        bestg[i] = og;
-                    }
-                }
+            for (int i = 0; i < 4; ++i) {
+                argmax_dpp<0xB1>(best[i], bestg[i]);    // quad_perm 1, 0, 3, 2
+                argmax_dpp<0x4E>(best[i], bestg[i]);    // quad_perm 2, 3, 0, 1
+                argmax_dpp<0x141>(best[i], bestg[i]);   // row_half_mirror
+                argmax_dpp<0x140>(best[i], bestg[i]);   // row_mirror
             }
             float arow[4];
 #pragma unroll
@@ -2069,6 +2090,7 @@ static bool init_keeps_correlation(const srt3d_params& p, const InitGrid& g) {
 // workspace: photon-count maxima of stretches of pixels (kInitWsHead bytes), the grid table
 // (B-operand fragments), then the atom's autocorrelation on 16 NT grid lags
 constexpr size_t kInitWsHead = (size_t)kInitBlocksMax * sizeof(int) + 256;
+constexpr size_t kInitTableLds = 32768;     // largest grid table the init kernel stages in LDS
 size_t init_ws_bytes(const srt3d_params& p) {
     const InitGrid g = init_grid(p);
     return kInitWsHead + (size_t)g.NT * g.KS * 64 * sizeof(float) + (size_t)16 * g.NT * sizeof(float);
@@ -2121,19 +2143,21 @@ hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int 
     int64_t blocks = ((int64_t)(P + 15) / 16 + 3) / 4;
     const int64_t cap = std::min<int64_t>((int64_t)cus * 8, kInitBlocksMax);
     if (blocks > cap) blocks = cap;
-#define SRT3D_INIT(KSM, RH)                                                                                      \
-    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((init_kernel<KK, KSM, RH>), dim3((unsigned)blocks), dim3(256), 0, s, z, n, \
-                                           st.hhat, st.scal, EB, rho, P, p.T, p.m, g.stride, g.G, g.KS, g.NT,      \
-                                           p.r_min, st.t[0], st.alpha[0], st.active[0], part, nparts, p.eta_t,     \
-                                           p.eta_a))
+#define SRT3D_INIT(KSM, RH, EBL)                                                                                  \
+    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((init_kernel<KK, KSM, RH, EBL>), dim3((unsigned)blocks), dim3(256),       \
+                                           EBL ? (size_t)tab * sizeof(float) : 0, s, z, n, st.hhat, st.scal, EB, rho,  \
+                                           P, p.T, p.m, g.stride, g.G, g.KS, g.NT, p.r_min, st.t[0], st.alpha[0],    \
+                                           st.active[0], part, nparts, p.eta_t, p.eta_a))
     const int ksn = g.KS > g.NT ? g.KS : g.NT;     // with the correlation kept, tiles index registers too
-    if (keep && ksn <= 4) { SRT3D_INIT(4, true); }
-    else if (keep && ksn <= 8) { SRT3D_INIT(8, true); }
-    else if (keep) { SRT3D_INIT(16, true); }
-    else if (g.KS <= 4) { SRT3D_INIT(4, false); }
-    else if (g.KS <= 8) { SRT3D_INIT(8, false); }
-    else if (g.KS <= 16) { SRT3D_INIT(16, false); }
-    else { SRT3D_INIT(32, false); }
+    // without the kept correlation, a grid table of up to 32 KB is read from LDS
+    const bool ebl = (size_t)tab * sizeof(float) <= kInitTableLds;
+    if (keep && ksn <= 4) { SRT3D_INIT(4, true, false); }
+    else if (keep && ksn <= 8) { SRT3D_INIT(8, true, false); }
+    else if (keep) { SRT3D_INIT(16, true, false); }
+    else if (g.KS <= 4) { if (ebl) { SRT3D_INIT(4, false, true); } else { SRT3D_INIT(4, false, false); } }
+    else if (g.KS <= 8) { if (ebl) { SRT3D_INIT(8, false, true); } else { SRT3D_INIT(8, false, false); } }
+    else if (g.KS <= 16) { if (ebl) { SRT3D_INIT(16, false, true); } else { SRT3D_INIT(16, false, false); } }
+    else { SRT3D_INIT(32, false, false); }
 #undef SRT3D_INIT
     return hipGetLastError();
 }
