@@ -346,27 +346,35 @@ def merge_points(st: State, p: Params) -> State:
     return State(t, a, act)
 
 
+def birth_correlation(st: State, z, hhat, p: Params):
+    """The birth step's sketched matched filter: on the grid tau = 0, s, 2s, ... the correlation
+    c[p, g] = Re sum_l conj(hhat_l) w_l exp(-i w_l tau_g) of the residual w = z - Phi(theta), -inf
+    at grid points closer than T/m (circularly) to an active point.  Also returns
+    sum_l |conj(hhat_l) w_l| per pixel, which bounds |c|.  Returns (tau [G], c [P, G], cabs [P])."""
+    T, m = p.T, p.m
+    z = np.asarray(z, dtype=np.complex128)
+    s = p.stride
+    G = -(-T // s)
+    tau = np.arange(G, dtype=np.int64) * s
+    ell = np.arange(1, m + 1, dtype=np.int64)
+    Eg = np.exp(-1j * 2.0 * np.pi * np.mod(tau[:, None] * ell[None, :], T) / T)    # [G, m]
+    w = z - np.einsum("pk,pkl->pl", np.where(st.active, st.alpha, 0.0), atoms(st.t, hhat, T))
+    c = ((np.conj(hhat) * w) @ Eg.T).real                                       # [P, G]
+    dist = np.abs(circ_diff(tau[None, None, :] - st.t[:, :, None], T))          # [P, K, G]
+    excluded = np.any(st.active[:, :, None] & (dist * m < T), axis=1)
+    return tau, np.where(excluded, -np.inf, c), np.abs(np.conj(hhat) * w).sum(1)
+
+
 def birth_points(st: State, z, n, hhat, p: Params) -> State:
     """Where a pixel has a free slot and photons: the sketched matched filter of the init
     (grid 0, s, 2s, ...) on the residual z - Phi(theta), restricted to grid points at circular
     distance >= T/m from every active point; the maximum (lowest tau on ties) with amplitude
     a = max(0, c / sum |hhat|^2) becomes a point in the first free slot iff n a >= r_min; then
     alpha is projected onto {alpha >= 0, sum alpha <= 1}."""
-    T, m, K = p.T, p.m, st.t.shape[1]
-    z = np.asarray(z, dtype=np.complex128)
     n = np.asarray(n, dtype=np.int64)
-    P = z.shape[0]
-    s = p.stride
-    G = -(-T // s)
-    tau = np.arange(G, dtype=np.int64) * s
-    ell = np.arange(1, m + 1, dtype=np.int64)
-    Eg = np.exp(-1j * 2.0 * np.pi * np.mod(tau[:, None] * ell[None, :], T) / T)    # [G, m]
+    P = st.t.shape[0]
     e2 = float(np.sum(np.abs(hhat) ** 2))
-    w = z - np.einsum("pk,pkl->pl", np.where(st.active, st.alpha, 0.0), atoms(st.t, hhat, T))
-    c = ((np.conj(hhat) * w) @ Eg.T).real                                       # [P, G]
-    dist = np.abs(circ_diff(tau[None, None, :] - st.t[:, :, None], T))          # [P, K, G]
-    excluded = np.any(st.active[:, :, None] & (dist * m < T), axis=1)
-    c = np.where(excluded, -np.inf, c)
+    tau, c, _ = birth_correlation(st, z, hhat, p)
     g = np.argmax(c, axis=1)
     rows = np.arange(P)
     best = c[rows, g]
@@ -510,5 +518,5 @@ __all__ = [
     "Params", "State", "wrap", "circ_diff", "project_capped_simplex", "step_sizes", "init_points",
     "data_step", "depth_denoise", "intensity_denoise", "background", "output", "iterate",
     "reconstruct", "chol_solve", "window_weight", "depth_denoise_loop", "intensity_denoise_loop",
-    "default_tau_z", "irf_spectrum", "atoms", "unit_phasors", "merge_points", "birth_points",
+    "default_tau_z", "irf_spectrum", "atoms", "unit_phasors", "merge_points", "birth_correlation", "birth_points",
 ]

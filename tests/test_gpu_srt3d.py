@@ -326,12 +326,53 @@ def test_merge_birth_stage_from_shared_state():
     da = np.abs(g.alpha - r.alpha).max(1)
     ok = same & (dt <= 1e-3) & (da <= 1e-4)
     born = r.active.sum(1) > st.active.sum(1)
-    merged = O.merge_points(st, fr.op).active.sum(1) < st.active.sum(1)     # freed slots may refill
-    print("births", int(born.sum()), "merges", int(merged.sum()), "pixels equal:", ok.mean())
+    rm = O.merge_points(st, fr.op)
+    merged = rm.active.sum(1) < st.active.sum(1)     # freed slots may refill
+    # The birth's grid argmax and its n a >= r_min test are decided in FP32 here and in FP64 in
+    # the oracle, so on a near-tie both answers are right.  A pixel that differs must be one:
+    # the GPU's new point sits on a grid point whose FP64 correlation is within the FP32
+    # rounding bound of the maximum (2m terms of |conj(hhat) w| at 2^-24 each, with inputs
+    # rounded to FP32: below 4e-6 sum |conj(hhat) w|), or the threshold test is that close;
+    # and the rest of the pixel is then what the oracle's birth gives for that choice.
+    tau, c, cabs = O.birth_correlation(rm, fr.zc, fr.hhat, fr.op)
+    e2 = float(np.sum(np.abs(fr.hhat) ** 2))
+    tol = 4e-6 * cabs
+    stride = fr.op.stride
+    explained = np.zeros(P, bool)
+    for i in np.flatnonzero(~ok):
+        free = ~rm.active[i]
+        if not free.any():
+            continue
+        s = int(np.argmax(free))
+        cmax = c[i].max()
+        if not np.isfinite(cmax):
+            continue
+        act = rm.active[i].copy()
+        t_exp = rm.t[i].copy()
+        a_exp = np.where(rm.active[i], rm.alpha[i], 0.0)
+        if g.active[i, s]:
+            gi = int(round(g.t[i, s] / stride))
+            if abs(g.t[i, s] - gi * stride) > 1e-3 or gi >= c.shape[1] or not c[i, gi] >= cmax - tol[i]:
+                continue
+            a_new = max(0.0, c[i, gi] / e2)
+            if fr.nn[i] * a_new < fr.op.r_min - fr.nn[i] * tol[i] / e2:
+                continue
+            act[s] = True
+            t_exp[s] = gi * stride
+            a_exp[s] = a_new
+        elif r.active[i, s]:
+            # the oracle's birth passed the threshold; the GPU's must have been that close
+            if abs(fr.nn[i] * max(0.0, cmax / e2) - fr.op.r_min) > fr.nn[i] * tol[i] / e2:
+                continue
+        a_exp = O.project_capped_simplex(a_exp[None], act[None])[0]
+        explained[i] = ((g.active[i] == act).all()
+                        and np.where(act, circ_abs(g.t[i] - t_exp, fr.spec.T), 0).max() <= 1e-3
+                        and np.abs(g.alpha[i] - a_exp).max() <= 1e-4)
+    print("births", int(born.sum()), "merges", int(merged.sum()), "pixels equal:", ok.mean(),
+          "differing:", int((~ok).sum()), "of which near-ties:", int(explained.sum()))
     assert born.sum() > 0.3 * drop.sum() and merged.sum() > 0
-    # the birth's grid argmax is decided in FP32 here and FP64 in the oracle: a peak between two
-    # grid points (stride 1 at T = 153) can flip to the neighbour on a near-tie
-    assert ok.mean() >= 0.99
+    assert (ok | explained).all()
+    assert ok.mean() >= 0.999
 
 
 def test_iterations_with_births_match_oracle():
