@@ -255,11 +255,12 @@ def precision_report(args):
           flush=True)
 
 
-def frames_in_flight(frame, w, params, irf, table, method: str, streams: int, rounds: int):
+def frames_in_flight(frame, w, params, irf, table, method: str, streams: int, rounds: int, ref_out):
     """`streams` frames at a time, each step (sketch + reconstruct) of a frame on its own HIP
     stream (default priority) with its own outputs and Reconstructor; `rounds` frames per stream.
     Returns frames/s over the streams * rounds frames, timed with events on the current stream
-    that every stream waits for and that waits for every stream."""
+    that every stream waits for and that waits for every stream, and whether every stream's
+    output equals `ref_out` (the single-stream step's) bit for bit."""
     import torch
 
     import paper_2203_00952_amd as srt
@@ -302,9 +303,10 @@ def frames_in_flight(frame, w, params, irf, table, method: str, streams: int, ro
     e[1].record(cur)
     torch.cuda.synchronize()
     ms = e[0].elapsed_time(e[1])
+    same = all(torch.equal(ln["out"][k], ref_out[k]) for ln in lanes for k in ref_out)
     del lanes
     return {"streams": streams, "frames": streams * rounds, "ms": ms,
-            "frames_per_s": streams * rounds / (ms * 1e-3)}
+            "frames_per_s": streams * rounds / (ms * 1e-3), "same_as_step": same}
 
 
 def serving_measure(count: int, budget_bytes: int, seed: int = 4):
@@ -564,7 +566,7 @@ def main():
     # independent, so a stream of them can run one per HIP stream; each stream does the whole
     # step (sketch + reconstruction) on its own buffers, and the stream's frames/s shows how much
     # of a lone frame's step is launch and latency rather than work
-    fif = frames_in_flight(frame, w, params, irf, table, args.sketch, streams=4, rounds=8)
+    fif = frames_in_flight(frame, w, params, irf, table, args.sketch, streams=4, rounds=8, ref_out=out)
 
     # the other sketch path on the same frame, for reference (outside the timed steps)
     other = "photon" if args.sketch == "binned" else "binned"
