@@ -89,8 +89,9 @@ def _plane(rng, rows, cols, d0, gmax, ic, jc):
 
 
 def _rect(rng, rows, cols):
-    h = int(rng.integers(max(1, rows // 8), max(2, rows // 2) + 1))
-    w = int(rng.integers(max(1, cols // 8), max(2, cols // 2) + 1))
+    # clamped after the draw, so frames of two or more rows and columns draw what they always did
+    h = min(rows, int(rng.integers(max(1, rows // 8), max(2, rows // 2) + 1)))
+    w = min(cols, int(rng.integers(max(1, cols // 8), max(2, cols // 2) + 1)))
     i0 = int(rng.integers(0, rows - h + 1))
     j0 = int(rng.integers(0, cols - w + 1))
     return i0, j0, h, w
