@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--graph", action="store_true",
                     help="replay the reconstruction's kernels from a HIP graph captured during the warm-up "
                          "(the line then also carries the host-launched figure as `eager`)")
+    ap.add_argument("--frames-in-flight", type=int, default=4,
+                    help="streams of the frames-in-flight leg in the default line (0 = skip; profile runs skip "
+                         "it so that the traced kernel times are those of lone frames)")
     ap.add_argument("--serving-requests", type=int, default=96,
                     help="requests of the short serving leg in the default line (0 = skip)")
     ap.add_argument("--budget-gib", type=float, default=4.0, help="serving workload: HBM budget")
@@ -598,7 +601,8 @@ def main():
     # independent, so a stream of them can run one per HIP stream; each stream does the whole
     # step (sketch + reconstruction) on its own buffers, and the stream's frames/s shows how much
     # of a lone frame's step is launch and latency rather than work
-    fif = frames_in_flight(frame, w, params, irf, table, args.sketch, streams=4, rounds=8, ref_out=out)
+    fif = (frames_in_flight(frame, w, params, irf, table, args.sketch, streams=args.frames_in_flight, rounds=8,
+                            ref_out=out) if args.frames_in_flight > 0 else None)
 
     # the other sketch path on the same frame, for reference (outside the timed steps)
     other = "photon" if args.sketch == "binned" else "binned"
