@@ -1754,6 +1754,61 @@ __device__ __forceinline__ void load_region(float* st, uint8_t* sa, float* sr, i
     }
 }
 
+// The same region in two halves, so that every load of a kernel's start can be issued before
+// the first of them is waited for: region_fetch issues this thread's NR rounds of loads into
+// registers, region_store writes them to LDS once they are needed.  The loads are unconditional
+// (cells outside the frame or past the region read the nearest frame cell, and region_store
+// writes zeros for them): a load under a branch would be waited for inside the branch, and
+// after the join the wait counter could no longer tell which loads are still in flight.
+// TA: depth and activity; WR: n * alpha.
+template <int K, int NR, bool TA, bool WR>
+struct RegionRegs {
+    float t[NR], a[NR];
+    int32_t n[NR];
+    uint32_t act[NR];
+    bool in[NR];
+};
+
+template <int K, int NR, bool TA, bool WR>
+__device__ __forceinline__ void region_fetch(RegionRegs<K, NR, TA, WR>& g, int EY, int E, int gi0, int gj0,
+                                             const IterArgs& A, const float* __restrict__ t_in,
+                                             const float* __restrict__ a_in, const uint8_t* __restrict__ act_in,
+                                             const int32_t* __restrict__ n) {
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+        const int idx = threadIdx.x + u * blockDim.x;
+        const int k = idx % K, cell = idx / K;
+        const int gi = gi0 + cell / E, gj = gj0 + cell % E;
+        g.in[u] = idx < EY * E * K && gi >= 0 && gi < A.rows && gj >= 0 && gj < A.cols;
+        const int gic = min(max(gi, 0), A.rows - 1), gjc = min(max(gj, 0), A.cols - 1);
+        const int64_t pc = (int64_t)gic * A.cols + gjc, q = pc * K + k;
+        if constexpr (TA) {
+            g.t[u] = t_in[q];
+            g.act[u] = act_in[q];
+        }
+        if constexpr (WR) {
+            g.a[u] = a_in[q];
+            g.n[u] = n[pc];
+        }
+    }
+}
+
+template <int K, int NR, bool TA, bool WR>
+__device__ __forceinline__ void region_store(const RegionRegs<K, NR, TA, WR>& g, float* st, uint8_t* sa, float* sr,
+                                             int EY, int E) {
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+        const int idx = threadIdx.x + u * blockDim.x;
+        if (idx < EY * E * K) {
+            if constexpr (TA) {
+                st[idx] = g.in[u] ? g.t[u] : 0.f;
+                sa[idx] = g.in[u] ? (uint8_t)g.act[u] : (uint8_t)0;
+            }
+            if constexpr (WR) sr[idx] = g.in[u] ? (float)g.n[u] * g.a[u] : 0.f;
+        }
+    }
+}
+
 template <int K, int R>
 __global__ __launch_bounds__(kTile * kTile) void depth_denoise_kernel(
     IterArgs A, const float* __restrict__ scal, const float* __restrict__ t_in, const float* __restrict__ a_in,
@@ -1859,9 +1914,24 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
     const bool dpix_in = dpi < A.rows && dpj < A.cols;
     const int dpix = dpix_in ? dpi * A.cols + dpj : 0;
     const bool prefetch = DS_NEXT && A.m <= kLanesPerPixel * kPrefetchSlice;
+    // Every load of the start goes out before the first wait: the state of the two regions, the
+    // IRF spectrum and this pixel's photon count first, the sketch prefetch last, so that the
+    // wait before the LDS stores covers the state and the prefetch stays in flight through the
+    // denoisers.  Without the stand-alone depth launch before (DD_DONE false) the tile + R
+    // region needs only n and alpha: its depths are the depth denoiser's output, and its
+    // activity flags are those of the wider region (copied in LDS during the depth phase).
+    constexpr int NR2 = (E2Y * E2 * K + kIterThreads - 1) / kIterThreads;
+    constexpr int NR1 = (E1Y * E1 * K + kIterThreads - 1) / kIterThreads;
+    RegionRegs<K, NR2, true, false> g2;
+    RegionRegs<K, NR1, DD_DONE, true> g1;
+    if constexpr (!DD_DONE) region_fetch(g2, E2Y, E2, i0 - 2 * R, j0 - 2 * R, A, t_in, a_in, act_in, n);
+    region_fetch(g1, E1Y, E1, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
+    static_assert(SRT3D_MAX_M_RECON <= kIterThreads, "one harmonic of the spectrum per thread");
+    const float2 hreg = reinterpret_cast<const float2*>(hhat)[min((int)threadIdx.x, A.m - 1)];
+    const int32_t n_own = n[dpix];                   // (pixel 0 for threads outside the frame: unused)
     float2 zr[kPrefetchSlice];
     if constexpr (DS_NEXT) {
-        if (prefetch) {
+        {   // issued whether or not it is used (m > 32 reads nothing: an empty descriptor)
             // A wave is one tile row of 16 pixels (kIterTX * kLanesPerPixel = 64 lanes).  Its
             // sketch rows are read through a buffer descriptor that starts at the wave's first
             // pixel and ends at the end of z: each lane reads kPrefetchSlice entries from the
@@ -1870,7 +1940,7 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
             static_assert(kIterTX * kLanesPerPixel == kWave, "one tile row per wave");
             const int lo = (sub * A.m) / kLanesPerPixel;
             const int64_t p0 = (int64_t)__builtin_amdgcn_readfirstlane(dpi) * A.cols + j0;
-            const int64_t left = p0 < A.P ? ((int64_t)A.P - p0) * A.m * 8 : 0;
+            const int64_t left = (prefetch && p0 < A.P) ? ((int64_t)A.P - p0) * A.m * 8 : 0;
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<float*>(z) + (p0 < A.P ? p0 : 0) * 2 * A.m, (short)0,
                 (int)(left < 0x7fffffff ? left : 0x7fffffff), kRsrcFlags);
@@ -1880,11 +1950,9 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
                 zr[j] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, j * 8, 0));
         }
     }
-    if constexpr (DS_NEXT)
-        for (int l = threadIdx.x; l < A.m; l += blockDim.x) s_h[l] = reinterpret_cast<const float2*>(hhat)[l];
-    if constexpr (!DD_DONE)
-        load_region<K, false>(s_t2, s_a2, nullptr, E2Y, E2, i0 - 2 * R, j0 - 2 * R, A, t_in, a_in, act_in, nullptr);
-    load_region<K, true>(s_td, s_a1, s_r1, E1Y, E1, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
+    if (DS_NEXT && (int)threadIdx.x < A.m) s_h[threadIdx.x] = hreg;
+    if constexpr (!DD_DONE) region_store(g2, s_t2, s_a2, nullptr, E2Y, E2);
+    region_store(g1, s_td, s_a1, s_r1, E1Y, E1);
     lds_barrier();
     const float Tf = (float)A.T, invT = A.invT, tau_z = scal[3];
     constexpr bool SPLIT_DD = !DD_DONE && K == 1 && E1Y * E1 <= kIterThreads / 2;
@@ -1903,6 +1971,7 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
             const int c2 = ci * E2 + cj;
             tq = s_t2[c2];
             fit = s_a2[c2] != 0;
+            if (!second) s_a1[idx] = s_a2[c2];                             // read after the barriers
             if (fit) {
                 dd_start<K, R>(M, b, !second);
                 if (second) {
@@ -1929,6 +1998,7 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
             const int k = idx % K, cell = idx / K;
             const int ci = cell / E1 + R, cj = cell % E1 + R;          // cell in the E2 region
             const int c2 = (ci * E2 + cj) * K + k;
+            s_a1[idx] = s_a2[c2];
             if (s_a2[c2]) s_td[idx] = dd_point<K, R>(s_t2, s_a2, E2, ci, cj, k, Tf, invT, tau_z, A.lambda_z);
             else s_td[idx] = s_t2[c2];
         }
@@ -1954,7 +2024,7 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
             dn += quad_xor2(dn);
             rt[k] = was[k] ? id_ratio(nm, dn) : 0.f;
         }
-        const float nq = (float)n[pix];
+        const float nq = (float)n_own;
         id_update<K>(rt, was, nq, A.r_min, ak, on);
         if constexpr (DS_NEXT) {
             // next data step
