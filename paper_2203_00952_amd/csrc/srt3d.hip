@@ -321,13 +321,26 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
                                                    float eta_a) {
     __shared__ float s_rho[RHO ? 16 * KSMAX : 1];
     __shared__ v4f s_C[RHO ? 4 * KSMAX * 64 : 1];     // [wave][column tile][lane]
-    extern __shared__ float s_eb[];                   // EBL: the grid table
+    extern __shared__ float4 s_eb4[];                 // EBL: the grid table
+    const float* s_eb = reinterpret_cast<const float*>(s_eb4);
     if constexpr (RHO) {
         for (int i = threadIdx.x; i < 16 * KSMAX; i += blockDim.x) s_rho[i] = i < 16 * NT ? rho[i] : 0.f;
         __syncthreads();
     }
     if constexpr (EBL) {
-        for (int i = threadIdx.x; i < NT * KS * 64; i += blockDim.x) s_eb[i] = EB[i];
+        // 16-byte pieces (the table starts 16-byte aligned and holds a multiple of 64 floats),
+        // eight rounds of loads in flight per thread before the first store
+        const float4* eb4 = reinterpret_cast<const float4*>(EB);
+        const int n4 = NT * KS * 16;
+        constexpr int U = 8;
+        for (int b = threadIdx.x; b < n4; b += U * blockDim.x) {
+            float4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = eb4[min(b + u * (int)blockDim.x, n4 - 1)];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (b + u * (int)blockDim.x < n4) s_eb4[b + u * blockDim.x] = v[u];
+        }
         __syncthreads();
     }
     // B fragment ks of column tile nt for this lane
@@ -341,23 +354,28 @@ __global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, 
     const int groups = (P + 15) / 16;
     const int waves_total = gridDim.x * (blockDim.x >> 6);
     const int l_first = kq / 2 + 1;                    // harmonic of ks = 0; +2 per ks
+    // Loads are unconditional (clamped indices, unused entries zeroed afterwards), so that all of
+    // a group's are in flight together rather than each waited for under its own branch.
     float2 hl[KSMAX];
 #pragma unroll
     for (int ks = 0; ks < KSMAX; ++ks) {
         const int k = 4 * ks + kq;
-        hl[ks] = (ks < KS && k < 2 * m) ? reinterpret_cast<const float2*>(hhat)[k / 2] : make_float2(0.f, 0.f);
+        const float2 h = reinterpret_cast<const float2*>(hhat)[min(k / 2, m - 1)];
+        hl[ks] = (ks < KS && k < 2 * m) ? h : make_float2(0.f, 0.f);
     }
     for (int grp = blockIdx.x * (blockDim.x >> 6) + wv; grp < groups; grp += waves_total) {
         const int prow = grp * 16 + r;
         const bool rv = prow < P;
+        const float2* zrow = reinterpret_cast<const float2*>(z + (int64_t)(rv ? prow : P - 1) * 2 * m);
         float2 w[KSMAX];
 #pragma unroll
         for (int ks = 0; ks < KSMAX; ++ks) {
             const int k = 4 * ks + kq;
-            w[ks] = (rv && ks < KS && k < 2 * m) ? reinterpret_cast<const float2*>(z + (int64_t)prow * 2 * m)[k / 2]
-                                                  : make_float2(0.f, 0.f);
+            const float2 v = zrow[min(k / 2, m - 1)];
+            w[ks] = (rv && ks < KS && k < 2 * m) ? v : make_float2(0.f, 0.f);
         }
-        const int np = rv ? n[prow] : 0;
+        const int np_raw = n[rv ? prow : P - 1];
+        const int np = rv ? np_raw : 0;
         int tau_row[K][4];                              // picks of C rows 4 kq + i
         int tau_mine[K];                                // picks of A row r
         float amp_mine[K];
@@ -530,14 +548,21 @@ struct GlobalSketch {
     const float2* zp;    // the pixel's sketch row
     const float2* hp;    // the IRF spectrum
     __device__ __forceinline__ float2 z(int l0, int) const { return zp[l0]; }
-    __device__ __forceinline__ float2 h(int l0) const { return hp[l0]; }
+    __device__ __forceinline__ float2 h(int l0, int) const { return hp[l0]; }
 };
 template <int MS>
 struct RegSketch {
     const float2* zr;    // zr[j] = z_{lo + j + 1}, j < hi - lo <= MS (registers after inlining)
     const float2* hs;    // the IRF spectrum in LDS
     __device__ __forceinline__ float2 z(int, int j) const { return zr[j]; }
-    __device__ __forceinline__ float2 h(int l0) const { return hs[l0]; }
+    __device__ __forceinline__ float2 h(int l0, int) const { return hs[l0]; }
+};
+template <int MS>
+struct RegSketchH {
+    const float2* zr;    // zr[j] = z_{lo + j + 1} and hr[j] = hhat_{lo + j + 1}, j < hi - lo <= MS
+    const float2* hr;
+    __device__ __forceinline__ float2 z(int, int j) const { return zr[j]; }
+    __device__ __forceinline__ float2 h(int, int j) const { return hr[j]; }
 };
 
 template <int K, int MS, class Src>
@@ -561,7 +586,7 @@ __device__ __forceinline__ void residual_pass(const Src& src, int lo, int hi, in
         const int l0 = lo + j;
         if (l0 >= hi) break;
         const int l = l0 + 1;
-        const float2 h = src.h(l0);
+        const float2 h = src.h(l0, j);
         const float2 zl = src.z(l0, j);
         float2 g[K];
         float2 e = make_float2(-zl.x, -zl.y);
@@ -636,10 +661,27 @@ __global__ __launch_bounds__(256) void data_step_kernel(IterArgs A, const float*
         on[k] = active[(int64_t)pix * K + k] != 0;
         any |= on[k];
     }
-    if (!any) return;
-    const GlobalSketch src{reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * A.m),
-                           reinterpret_cast<const float2*>(hhat)};
-    data_point<K, kMaxSlice>(src, sub, A.m, A.T, A.invT, A.twoinvT, (float)n[pix], scal[1], scal[2], tk, ak, on);
+    const float nq = (float)n[pix];
+    const float2* zrow = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * A.m);
+    const float2* hh = reinterpret_cast<const float2*>(hhat);
+    if (A.m <= kLanesPerPixel * kPrefetchSlice) {
+        // the lane's slice of the sketch and of the spectrum, loaded with the state above (clamped
+        // to the row, entries past the slice unused), so that every load is in flight at once
+        const int lo = (sub * A.m) / kLanesPerPixel;
+        float2 zr[kPrefetchSlice], hr[kPrefetchSlice];
+#pragma unroll
+        for (int j = 0; j < kPrefetchSlice; ++j) {
+            zr[j] = zrow[min(lo + j, A.m - 1)];
+            hr[j] = hh[min(lo + j, A.m - 1)];
+        }
+        if (!any) return;
+        const RegSketchH<kPrefetchSlice> src{zr, hr};
+        data_point<K, kPrefetchSlice>(src, sub, A.m, A.T, A.invT, A.twoinvT, nq, scal[1], scal[2], tk, ak, on);
+    } else {
+        if (!any) return;
+        const GlobalSketch src{zrow, hh};
+        data_point<K, kMaxSlice>(src, sub, A.m, A.T, A.invT, A.twoinvT, nq, scal[1], scal[2], tk, ak, on);
+    }
     if (sub != 0) return;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -676,7 +718,7 @@ __device__ __forceinline__ void smle_start(const Src& src, int lo, int hi, int s
         for (int j = 0; j < MS; ++j) {
             const int l0 = lo + j;
             if (l0 >= hi) break;
-            const float2 g = cmul(src.h(l0), phasor(l0 + 1, tk[k], T, invT, twoinvT));
+            const float2 g = cmul(src.h(l0, j), phasor(l0 + 1, tk[k], T, invT, twoinvT));
             const float2 zl = src.z(l0, j);
             c += g.x * zl.x + g.y * zl.y;
         }
@@ -697,7 +739,7 @@ __device__ __forceinline__ float smle_residual(const Src& src, int lo, int hi, i
     for (int j = 0; j < MS; ++j) {
         const int l0 = lo + j;
         if (l0 >= hi) break;
-        const float2 h = src.h(l0);
+        const float2 h = src.h(l0, j);
         const float2 zl = src.z(l0, j);
         float2 e = make_float2(-zl.x, -zl.y);
 #pragma unroll
@@ -2055,7 +2097,11 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
 }
 
 // ----------------------------------------------------------------------------- finalize
-template <int K>
+// RB >= 0: the background radius fixed at compile time, the window unrolled and every load
+// unconditional (clamped into the frame, outside cells masked out of the sums: adding +0 changes
+// nothing), so they are all in flight together; RB < 0: the radius A.Rb at run time.  Both sum
+// the same terms in the same order.
+template <int K, int RB>
 __global__ __launch_bounds__(256) void finalize_kernel(IterArgs A, const int32_t* __restrict__ n,
                                                        const float* __restrict__ t_in,
                                                        const float* __restrict__ a_in,
@@ -2065,7 +2111,43 @@ __global__ __launch_bounds__(256) void finalize_kernel(IterArgs A, const int32_t
     const int pix = blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= A.P) return;
     const int i = pix / A.cols, j = pix - (pix / A.cols) * A.cols;
-    if (bg) {
+    // the pixel's own state, loaded with the window's below
+    float t_own[K], a_own[K];
+    uint32_t act_own[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t q = (int64_t)pix * K + k;
+        t_own[k] = t_in[q];
+        a_own[k] = a_in[q];
+        act_own[k] = act_in[q];
+    }
+    const int32_t n_own = n[pix];
+    if (RB >= 0 && bg) {
+        constexpr int W = 2 * (RB > 0 ? RB : 0) + 1;
+        float nb[W * W], sa[W * W];
+        bool in[W * W];
+#pragma unroll
+        for (int w = 0; w < W * W; ++w) {
+            const int ii = i + w / W - (W / 2), jj = j + w % W - (W / 2);
+            in[w] = ii >= 0 && ii < A.rows && jj >= 0 && jj < A.cols;
+            const int64_t nbp = (int64_t)min(max(ii, 0), A.rows - 1) * A.cols + min(max(jj, 0), A.cols - 1);
+            nb[w] = (float)n[nbp];
+            sa[w] = 0.f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float av = a_in[nbp * K + k];
+                sa[w] += act_in[nbp * K + k] ? av : 0.f;
+            }
+        }
+        float s = 0.f;
+        int c = 0;
+#pragma unroll
+        for (int w = 0; w < W * W; ++w) {
+            s += in[w] ? nb[w] * fmaxf(0.f, 1.f - sa[w]) / (float)A.T : 0.f;
+            c += in[w] ? 1 : 0;
+        }
+        bg[pix] = s / (float)c;
+    } else if (bg) {
         float s = 0.f;
         int c = 0;
         for (int di = -A.Rb; di <= A.Rb; ++di) {
@@ -2088,13 +2170,12 @@ __global__ __launch_bounds__(256) void finalize_kernel(IterArgs A, const int32_t
     // slots sorted by depth, inactive last (stable)
     float tk[K], rk[K];
     bool on[K];
-    const float nq = (float)n[pix];
+    const float nq = (float)n_own;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const int64_t q = (int64_t)pix * K + k;
-        on[k] = act_in[q] != 0;
-        tk[k] = on[k] ? t_in[q] : 0.f;
-        rk[k] = on[k] ? nq * a_in[q] : 0.f;
+        on[k] = act_own[k] != 0;
+        tk[k] = on[k] ? t_own[k] : 0.f;
+        rk[k] = on[k] ? nq * a_own[k] : 0.f;
     }
     for (int a = 1; a < K; ++a)
         for (int b = a; b > 0; --b) {
@@ -2393,7 +2474,11 @@ hipError_t launch_finalize(const srt3d_params& p, const int32_t* n, const srt3d_
                            float* intensity, uint8_t* active, float* bg, hipStream_t s) {
     const IterArgs A = make_args(p);
     const int c = st.cur;
-    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((finalize_kernel<KK>), pixel_grid(A.P, 256), dim3(256), 0, s, A, n,
+    if (p.Rb == 1)
+        SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((finalize_kernel<KK, 1>), pixel_grid(A.P, 256), dim3(256), 0, s, A, n,
+                                               st.t[c], st.alpha[c], st.active[c], depth, intensity, active, bg))
+    else
+    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((finalize_kernel<KK, -1>), pixel_grid(A.P, 256), dim3(256), 0, s, A, n,
                                            st.t[c], st.alpha[c], st.active[c], depth, intensity, active, bg));
     return hipGetLastError();
 }
