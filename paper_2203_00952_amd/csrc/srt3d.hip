@@ -1772,33 +1772,10 @@ __device__ __forceinline__ int2 xcd_tile() {
     return make_int2(t % nx, t / nx);
 }
 
-// Load an (EY x E cells) x K region with origin (gi0, gj0) into LDS (row stride E cells); cells
-// outside the frame are inactive with depth 0.  With WITH_R the intensity n * alpha is loaded too.
-template <int K, bool WITH_R>
-__device__ __forceinline__ void load_region(float* st, uint8_t* sa, float* sr, int EY, int E, int gi0, int gj0,
-                                            const IterArgs& A, const float* __restrict__ t_in,
-                                            const float* __restrict__ a_in, const uint8_t* __restrict__ act_in,
-                                            const int32_t* __restrict__ n) {
-    for (int idx = threadIdx.x; idx < EY * E * K; idx += blockDim.x) {
-        const int k = idx % K, cell = idx / K;
-        const int gi = gi0 + cell / E, gj = gj0 + cell % E;
-        float tv = 0.f, rv = 0.f;
-        uint8_t av = 0;
-        if (gi >= 0 && gi < A.rows && gj >= 0 && gj < A.cols) {
-            const int64_t q = ((int64_t)gi * A.cols + gj) * K + k;
-            tv = t_in[q];
-            av = act_in[q];
-            if constexpr (WITH_R) rv = (float)n[(int64_t)gi * A.cols + gj] * a_in[q];
-        }
-        st[idx] = tv;
-        sa[idx] = av;
-        if constexpr (WITH_R) sr[idx] = rv;
-    }
-}
-
-// The same region in two halves, so that every load of a kernel's start can be issued before
-// the first of them is waited for: region_fetch issues this thread's NR rounds of loads into
-// registers, region_store writes them to LDS once they are needed.  The loads are unconditional
+// An (EY x E cells) x K region with origin (gi0, gj0), read into LDS (row stride E cells; cells
+// outside the frame inactive with depth 0) in two halves, so that every load of a kernel's start
+// can be issued before the first of them is waited for: region_fetch issues this thread's NR
+// rounds of loads into registers, region_store writes them to LDS once they are needed.  The loads are unconditional
 // (cells outside the frame or past the region read the nearest frame cell, and region_store
 // writes zeros for them): a load under a branch would be waited for inside the branch, and
 // after the join the wait counter could no longer tell which loads are still in flight.
@@ -1861,7 +1838,11 @@ __global__ __launch_bounds__(kTile * kTile) void depth_denoise_kernel(
     __shared__ uint8_t s_a[E * E * K];
     const int2 tile = xcd_tile();
     const int i0 = tile.y * kTile, j0 = tile.x * kTile;
-    load_region<K, false>(s_t, s_a, nullptr, E, E, i0 - R, j0 - R, A, t_in, a_in, act_in, nullptr);
+    {
+        RegionRegs<K, (E * E * K + kTile * kTile - 1) / (kTile * kTile), true, false> g;
+        region_fetch(g, E, E, i0 - R, j0 - R, A, t_in, a_in, act_in, nullptr);
+        region_store(g, s_t, s_a, nullptr, E, E);
+    }
     __syncthreads();
     const int ti = threadIdx.x / kTile, tj = threadIdx.x % kTile;
     const int i = i0 + ti, j = j0 + tj;
@@ -1888,7 +1869,11 @@ __global__ __launch_bounds__(kTile * kTile) void intensity_denoise_kernel(
     __shared__ uint8_t s_a[E * E * K];
     const int2 tile = xcd_tile();
     const int i0 = tile.y * kTile, j0 = tile.x * kTile;
-    load_region<K, true>(s_t, s_a, s_r, E, E, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
+    {
+        RegionRegs<K, (E * E * K + kTile * kTile - 1) / (kTile * kTile), true, true> g;
+        region_fetch(g, E, E, i0 - R, j0 - R, A, t_in, a_in, act_in, n);
+        region_store(g, s_t, s_a, s_r, E, E);
+    }
     __syncthreads();
     const int ti = threadIdx.x / kTile, tj = threadIdx.x % kTile;
     const int i = i0 + ti, j = j0 + tj;
