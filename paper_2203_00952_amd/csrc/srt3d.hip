@@ -1027,7 +1027,13 @@ __device__ __forceinline__ float seg_sum(float v) {
 template <int K>
 __device__ __forceinline__ void w_residual(const float2* __restrict__ zp, const float2* __restrict__ h2, int i, int m,
                                            int T, const float* tk, const float* ak, const bool* on, float& r,
-                                           float* jc) {
+                                           float* jc);
+
+// The same with this lane's spectrum and sketch entries (h = hhat_l, zl = z_l, l the lane's
+// harmonic) already in registers.
+template <int K>
+__device__ __forceinline__ void w_residual_v(float2 h, float2 zl, int i, int m, int T, const float* tk,
+                                             const float* ak, const bool* on, float& r, float* jc) {
     const float Tf = (float)T, invT = 1.0f / Tf, twoinvT = 2.0f / Tf;
     r = 0.f;
 #pragma unroll
@@ -1035,7 +1041,6 @@ __device__ __forceinline__ void w_residual(const float2* __restrict__ zp, const 
     if (i >= 2 * m) return;
     const bool re = i < m;
     const int l = (re ? i : i - m) + 1;
-    const float2 h = h2[l - 1];
     const float w = 6.283185307179586f * (float)l * invT;
     float2 phi = make_float2(0.f, 0.f);
 #pragma unroll
@@ -1048,8 +1053,15 @@ __device__ __forceinline__ void w_residual(const float2* __restrict__ zp, const 
         jc[k] = re ? -ak[k] * w * g.y : ak[k] * w * g.x;
         jc[K + k] = re ? g.x : g.y;
     }
-    const float2 zl = zp[l - 1];
     r = re ? zl.x - phi.x : zl.y - phi.y;
+}
+
+template <int K>
+__device__ __forceinline__ void w_residual(const float2* __restrict__ zp, const float2* __restrict__ h2, int i, int m,
+                                           int T, const float* tk, const float* ak, const bool* on, float& r,
+                                           float* jc) {
+    const int l = i < 2 * m ? (i < m ? i : i - m) + 1 : 1;
+    w_residual_v<K>(h2[l - 1], zp[l - 1], i, m, T, tk, ak, on, r, jc);
 }
 
 // Row pitch (floats) of a segment's M2 x M2 LDS matrix: unpadded, so that four waves of two
@@ -1451,6 +1463,12 @@ __global__ __launch_bounds__(256) void wdata_kernel(IterArgs A, const float* __r
         ak[k] = a_io[q];
         on[k] = act[q] != 0;
     }
+    // the lane's spectrum and sketch entries, the counts and the weight bound, loaded with the state
+    const int lh = i < twom ? (i < m ? i : i - m) : 0;     // harmonic - 1 of this lane's component
+    const float2 h_own = hhat[lh];
+    const float2 z_own = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m)[lh];
+    const int32_t n_own = n[pix];
+    const unsigned int nw_raw = *nw_bits;
     float wrow[M2];
     {
         constexpr int kMaxTri = w_tri(M2);
@@ -1460,7 +1478,16 @@ __global__ __launch_bounds__(256) void wdata_kernel(IterArgs A, const float* __r
         const int np = A.P - p0 < kPPW ? A.P - p0 : kPPW;     // its pixels in the frame (>= 1)
         const float4* src = reinterpret_cast<const float4*>(W + (int64_t)p0 * tri);
         float4* dst = reinterpret_cast<float4*>(s_w[wv]);
-        for (int q = lane; q < np * tri / 4; q += 64) dst[q] = src[q];
+        // every round's 16-byte load in flight before the first store (clamped to the last
+        // piece, which is then copied again)
+        constexpr int kRounds = (kPPW * kMaxTri / 4 + 63) / 64;
+        const int nq4 = np * tri / 4;
+        float4 wv4[kRounds];
+#pragma unroll
+        for (int u = 0; u < kRounds; ++u) wv4[u] = src[min(lane + 64 * u, nq4 - 1)];
+#pragma unroll
+        for (int u = 0; u < kRounds; ++u)
+            if (lane + 64 * u < nq4) dst[lane + 64 * u] = wv4[u];
         const float* tw = s_w[wv] + (valid ? seg : 0) * tri;  // (same wave: LDS order suffices)
 #pragma unroll
         for (int c = 0; c < M2; ++c) {
@@ -1470,18 +1497,17 @@ __global__ __launch_bounds__(256) void wdata_kernel(IterArgs A, const float* __r
         }
     }
     // the W = I steps with n_max replaced by n_w
-    const float nw = __uint_as_float(*nw_bits);
+    const float nw = __uint_as_float(nw_raw);
     const float gam_t = nw > 0.f ? scal[1] * (scal[0] / nw) : 0.f;
     const float gam_a = nw > 0.f ? scal[2] * (scal[0] / nw) : 0.f;
-    const float2* zp = reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * m);
-    const float nq = (float)n[pix];
+    const float nq = (float)n_own;
     // g = 2 n J^T W e at (tt, ak); e goes to LDS once and every lane of the segment reads it
     // whole, four entries at a time (broadcast reads)
     __shared__ __align__(16) float s_e[kWaves][64];
     float* se = s_e[wv] + base;
     auto grad = [&](const float* tt, float* g) {
         float r, jc[2 * K];
-        w_residual<K>(zp, hhat, i, m, T, tt, ak, on, r, jc);          // r = z - Phi
+        w_residual_v<K>(h_own, z_own, i, m, T, tt, ak, on, r, jc);    // r = z - Phi
         se[i] = -r;                                                    // e
         float v = 0.f;
 #pragma unroll
