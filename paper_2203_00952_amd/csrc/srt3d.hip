@@ -2000,7 +2000,7 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
             const int voff = (dtj * A.m + lo) * 8;
 #pragma unroll
             for (int j = 0; j < kPrefetchSlice; ++j)
-                zr[j] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, j * 8, 0));
+                zr[j] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff + j * 8, 0, 0));
         }
     }
     if (DS_NEXT && (int)threadIdx.x < A.m) s_h[threadIdx.x] = hreg;
