@@ -2003,11 +2003,14 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
                 zr[j] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff + j * 8, 0, 0));
         }
     }
+    // the frame constants (depth gate, step sizes) are read before the barrier, so that their
+    // scalar loads are not waited for behind it
+    const float tau_z = scal[3], gam_t = scal[1], gam_a = scal[2];
     if (DS_NEXT && (int)threadIdx.x < A.m) s_h[threadIdx.x] = hreg;
     if constexpr (!DD_DONE) region_store(g2, s_t2, s_a2, nullptr, E2Y, E2);
     region_store(g1, s_td, s_a1, s_r1, E1Y, E1);
     lds_barrier();
-    const float Tf = (float)A.T, invT = A.invT, tau_z = scal[3];
+    const float Tf = (float)A.T, invT = A.invT;
     constexpr bool SPLIT_DD = !DD_DONE && K == 1 && E1Y * E1 <= kIterThreads / 2;
     if constexpr (SPLIT_DD) {
         // depth denoiser on the tile + R ring, one cell per thread of each half of the block:
@@ -2087,11 +2090,11 @@ __global__ __launch_bounds__(kIterThreads) void iteration_kernel(
             if (any) {
                 if (prefetch) {
                     const RegSketch<kPrefetchSlice> src{zr, s_h};
-                    data_point<K, kPrefetchSlice>(src, sub, A.m, A.T, A.invT, A.twoinvT, nq, scal[1], scal[2], tk, ak,
+                    data_point<K, kPrefetchSlice>(src, sub, A.m, A.T, A.invT, A.twoinvT, nq, gam_t, gam_a, tk, ak,
                                                   on);
                 } else {
                     const GlobalSketch src{reinterpret_cast<const float2*>(z + (int64_t)pix * 2 * A.m), s_h};
-                    data_point<K, kMaxSlice>(src, sub, A.m, A.T, A.invT, A.twoinvT, nq, scal[1], scal[2], tk, ak, on);
+                    data_point<K, kMaxSlice>(src, sub, A.m, A.T, A.invT, A.twoinvT, nq, gam_t, gam_a, tk, ak, on);
                 }
             }
         }
