@@ -259,9 +259,15 @@ __global__ __launch_bounds__(kSetupThreads) void frame_setup_kernel(
         const int b = blockIdx.x - tb - 1;
         const int64_t base = (int64_t)b * kSetupThreads * cpt + threadIdx.x;
         int v = 0;
-        for (int i = 0; i < cpt; ++i) {
-            const int64_t q = base + (int64_t)i * kSetupThreads;
-            if (q < P) v = max(v, n[q]);
+        // 16 counts per round, all loaded (clamped into the frame) before the first is used
+        constexpr int U = 16;
+        for (int i0 = 0; i0 < cpt; i0 += U) {
+            int c[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) c[u] = n[min(base + (int64_t)(i0 + u) * kSetupThreads, (int64_t)P - 1)];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i0 + u < cpt && base + (int64_t)(i0 + u) * kSetupThreads < P) v = max(v, c[u]);
         }
         for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
         if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
