@@ -316,8 +316,13 @@ __device__ __forceinline__ void argmax_dpp(float& best, int& bestg) {
 
 // EBL: the grid table is first copied to LDS (dynamic shared memory of NT KS 64 floats), so
 // the B operands of every column tile are LDS reads instead of L2 round trips.
+// Workgroup size: 1024 threads when the grid table is copied to LDS without the per-wave
+// correlation tiles (one copy per 16 waves instead of per 4, so fewer workgroups read the same
+// table lines from L2 at the same moment), else 256.
+template <bool EBL, bool RHO, int KSMAX> constexpr int kInitThreads = (EBL && !RHO && KSMAX <= 8) ? 1024 : 256;
+
 template <int K, int KSMAX, bool RHO, bool EBL>
-__global__ __launch_bounds__(256) void init_kernel(const float* __restrict__ z, const int32_t* __restrict__ n,
+__global__ __launch_bounds__((kInitThreads<EBL, RHO, KSMAX>)) void init_kernel(const float* __restrict__ z, const int32_t* __restrict__ n,
                                                    const float* __restrict__ hhat, float* __restrict__ scal,
                                                    const float* __restrict__ EB, const float* __restrict__ rho, int P,
                                                    int T, int m, int stride, int G, int KS, int NT, float r_min,
@@ -2311,14 +2316,18 @@ hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int 
     if (e != hipSuccess) return e;
     int cus = 0;
     if ((e = current_device_cus(&cus)) != hipSuccess) return e;
-    int64_t blocks = ((int64_t)(P + 15) / 16 + 3) / 4;
-    const int64_t cap = std::min<int64_t>((int64_t)cus * 8, kInitBlocksMax);
-    if (blocks > cap) blocks = cap;
+    const int64_t groups = ((int64_t)P + 15) / 16;            // 16 pixels per wave
 #define SRT3D_INIT(KSM, RH, EBL)                                                                                  \
-    SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((init_kernel<KK, KSM, RH, EBL>), dim3((unsigned)blocks), dim3(256),       \
-                                           EBL ? (size_t)tab * sizeof(float) : 0, s, z, n, st.hhat, st.scal, EB, rho,  \
-                                           P, p.T, p.m, g.stride, g.G, g.KS, g.NT, p.r_min, st.t[0], st.alpha[0],    \
-                                           st.active[0], part, nparts, p.eta_t, p.eta_a))
+    {                                                                                                             \
+        constexpr int TH = kInitThreads<EBL, RH, KSM>;                                                                \
+        int64_t blocks = (groups + TH / 64 - 1) / (TH / 64);                                                      \
+        const int64_t cap = std::min<int64_t>((int64_t)cus * (8 * 256 / TH), kInitBlocksMax);                      \
+        if (blocks > cap) blocks = cap;                                                                           \
+        SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((init_kernel<KK, KSM, RH, EBL>), dim3((unsigned)blocks), dim3(TH),   \
+                                               EBL ? (size_t)tab * sizeof(float) : 0, s, z, n, st.hhat, st.scal, EB, \
+                                               rho, P, p.T, p.m, g.stride, g.G, g.KS, g.NT, p.r_min, st.t[0],        \
+                                               st.alpha[0], st.active[0], part, nparts, p.eta_t, p.eta_a))          \
+    }
     const int ksn = g.KS > g.NT ? g.KS : g.NT;     // with the correlation kept, tiles index registers too
     // without the kept correlation, a grid table of up to 32 KB is read from LDS
     const bool ebl = (size_t)tab * sizeof(float) <= kInitTableLds;
