@@ -61,6 +61,13 @@ def layered(dev, rows=48, cols=40, **pk):
     return Frame(spec, 32, 3, dev, r_min=100.0, **pk)
 
 
+def wide(dev, **pk):
+    """384 x 512 pixels at the throughput frame's T and m: more 16-pixel groups than one pass of
+    init's workgroups covers, so each wave takes several (the LDS-table form, 1024 threads)."""
+    spec = synth.FrameSpec(384, 512, 4096, 8.0, 100.0, 1.0, 1, seed=61)
+    return Frame(spec, 16, 1, dev, **pk)
+
+
 def pixel_pass(d_g, a_g, d_r, a_r, T, tol=1.0):
     """Pixel passes iff the active sets agree and active depths agree within `tol` bins."""
     a_g = a_g.astype(bool)
@@ -71,7 +78,7 @@ def pixel_pass(d_g, a_g, d_r, a_r, T, tol=1.0):
 
 
 # ----------------------------------------------------------------------------- constants and init
-@pytest.mark.parametrize("make", [tiny, layered])
+@pytest.mark.parametrize("make", [tiny, layered, wide])
 def test_frame_constants(make):
     dev = device()
     fr = make(dev)
@@ -86,7 +93,7 @@ def test_frame_constants(make):
     np.testing.assert_allclose(sc[3], fr.tau_z, rtol=1e-6)
 
 
-@pytest.mark.parametrize("make", [tiny, layered])
+@pytest.mark.parametrize("make", [tiny, layered, wide])
 def test_init_matches_oracle(make):
     dev = device()
     fr = make(dev)
