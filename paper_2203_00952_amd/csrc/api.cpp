@@ -258,8 +258,10 @@ size_t srt3d_init_workspace_bytes(const srt3d_params* p) {
     return init_ws_bytes(*p);
 }
 
-int srt3d_init(const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len, int32_t irf_origin,
-               const srt3d_params* p, srt3d_state* st, void* d_ws, size_t ws_bytes, void* stream) {
+namespace {
+// ds: the first data step of the iterations that follow runs inside the init launch
+int init_impl(const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len, int32_t irf_origin,
+              const srt3d_params* p, srt3d_state* st, void* d_ws, size_t ws_bytes, void* stream, bool ds) {
     int rc = check_params(p);
     if (rc != SRT3D_OK) return rc;
     if ((rc = check_state(st)) != SRT3D_OK) return rc;
@@ -268,7 +270,13 @@ int srt3d_init(const float* d_z, const int32_t* d_n, const double* d_irf, int32_
     if (!aligned(d_ws, 16) || !aligned(d_z, 8) || !aligned(st->hhat, 8)) return SRT3D_EINVAL;
     if (ws_bytes < init_ws_bytes(*p)) return SRT3D_ENOMEM;
     st->cur = 0;
-    return dev_status(launch_init(d_z, d_n, d_irf, irf_len, irf_origin, *p, *st, d_ws, as_stream(stream)));
+    return dev_status(launch_init(d_z, d_n, d_irf, irf_len, irf_origin, *p, *st, d_ws, as_stream(stream), ds));
+}
+}  // namespace
+
+int srt3d_init(const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len, int32_t irf_origin,
+               const srt3d_params* p, srt3d_state* st, void* d_ws, size_t ws_bytes, void* stream) {
+    return init_impl(d_z, d_n, d_irf, irf_len, irf_origin, p, st, d_ws, ws_bytes, stream, false);
 }
 
 int srt3d_smle(const float* d_z, const int32_t* d_n, const double* d_irf, int32_t irf_len, int32_t irf_origin,
@@ -362,8 +370,10 @@ int srt3d_step(srt3d_state* st, const float* d_z, const int32_t* d_n, const srt3
     return SRT3D_OK;
 }
 
-int srt3d_iterate(srt3d_state* st, const float* d_z, const int32_t* d_n, const srt3d_params* p, int32_t iters,
-                  void* stream) {
+namespace {
+// first_done: the first data step already ran (inside the init launch)
+int iterate_impl(srt3d_state* st, const float* d_z, const int32_t* d_n, const srt3d_params* p, int32_t iters,
+                 void* stream, bool first_done) {
     int rc = check_params(p);
     if (rc != SRT3D_OK) return rc;
     if ((rc = check_state(st)) != SRT3D_OK) return rc;
@@ -374,7 +384,7 @@ int srt3d_iterate(srt3d_state* st, const float* d_z, const int32_t* d_n, const s
     // pixel a depth-denoiser launch and the fused rest.  With merge/birth stages, an iteration
     // followed by one ends without the data step, which then follows the stage.
     hipStream_t s = as_stream(stream);
-    if (launch_data_step(*p, d_z, d_n, *st, st->cur, s) != hipSuccess) return SRT3D_EDEVICE;
+    if (!first_done && launch_data_step(*p, d_z, d_n, *st, st->cur, s) != hipSuccess) return SRT3D_EDEVICE;
     for (int it = 0; it < iters; ++it) {
         const bool birth = p->birth_every > 0 && (it + 1) % p->birth_every == 0 && it + 1 < iters;
         int next = st->cur;
@@ -387,6 +397,12 @@ int srt3d_iterate(srt3d_state* st, const float* d_z, const int32_t* d_n, const s
         }
     }
     return SRT3D_OK;
+}
+}  // namespace
+
+int srt3d_iterate(srt3d_state* st, const float* d_z, const int32_t* d_n, const srt3d_params* p, int32_t iters,
+                  void* stream) {
+    return iterate_impl(st, d_z, d_n, p, iters, stream, false);
 }
 
 namespace {
@@ -445,9 +461,13 @@ int srt3d_reconstruct(const float* d_z, const int32_t* d_n, const double* d_irf,
                       int32_t irf_origin, const srt3d_params* p, srt3d_state* st, float* d_depth,
                       float* d_intensity, uint8_t* d_active, float* d_bg, void* d_ws, size_t ws_bytes,
                       void* stream) {
-    int rc = srt3d_init(d_z, d_n, d_irf, irf_len, irf_origin, p, st, d_ws, ws_bytes, stream);
+    // the iterations' first data step runs inside the init launch (one launch fewer; the same state
+    // as srt3d_init followed by srt3d_iterate)
+    if (!p) return SRT3D_EINVAL;
+    const bool fuse = p->iters > 0;
+    int rc = init_impl(d_z, d_n, d_irf, irf_len, irf_origin, p, st, d_ws, ws_bytes, stream, fuse);
     if (rc != SRT3D_OK) return rc;
-    if ((rc = srt3d_iterate(st, d_z, d_n, p, p->iters, stream)) != SRT3D_OK) return rc;
+    if ((rc = iterate_impl(st, d_z, d_n, p, p->iters, stream, fuse)) != SRT3D_OK) return rc;
     return srt3d_finalize(st, d_n, p, d_depth, d_intensity, d_active, d_bg, stream);
 }
 

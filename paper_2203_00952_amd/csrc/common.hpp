@@ -98,8 +98,10 @@ hipError_t launch_sketch_hist(const uint16_t* hist, int P, int T, int m, int pre
                               float* z, int32_t* n, hipStream_t s);
 size_t hist_ws_bytes(int T, int m, int precision);
 
+// ds: the iteration's first data step runs in the same launch (the state it leaves is that of
+// init followed by launch_data_step)
 hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int irf_len, int irf_origin,
-                       const srt3d_params& p, const srt3d_state& st, void* ws, hipStream_t s);
+                       const srt3d_params& p, const srt3d_state& st, void* ws, hipStream_t s, bool ds = false);
 hipError_t launch_data_step(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st,
                             int cur, hipStream_t s);
 hipError_t launch_smle(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st, int starts,

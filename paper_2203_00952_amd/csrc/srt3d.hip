@@ -290,13 +290,27 @@ __global__ __launch_bounds__(kSetupThreads) void frame_setup_kernel(
 }
 
 // n_max and the step sizes of eq. (8).
-__device__ __forceinline__ void step_sizes_store(int nmax_i, int K, float eta_t, float eta_a, float* __restrict__ scal) {
+__device__ __forceinline__ void step_sizes(int nmax_i, int K, float eta_t, float eta_a, const float* __restrict__ scal,
+                                           float& gam_t, float& gam_a) {
     const double nmax = (double)nmax_i;
     const double e2 = (double)scal[4], et = (double)scal[5];
-    scal[0] = (float)nmax;
-    scal[1] = nmax > 0 ? (float)((double)eta_t / (2.0 * nmax * et)) : 0.f;
-    scal[2] = nmax > 0 ? (float)((double)eta_a / (2.0 * nmax * K * e2)) : 0.f;
+    gam_t = nmax > 0 ? (float)((double)eta_t / (2.0 * nmax * et)) : 0.f;
+    gam_a = nmax > 0 ? (float)((double)eta_a / (2.0 * nmax * K * e2)) : 0.f;
 }
+__device__ __forceinline__ void step_sizes_store(int nmax_i, int K, float eta_t, float eta_a, float* __restrict__ scal) {
+    float gam_t, gam_a;
+    step_sizes(nmax_i, K, eta_t, eta_a, scal, gam_t, gam_a);
+    scal[0] = (float)(double)nmax_i;
+    scal[1] = gam_t;
+    scal[2] = gam_a;
+}
+
+// The first data step of an iteration, fused into init (defined with the data step below).
+template <int K>
+__device__ void init_data_step(const IterArgs& A, const float* __restrict__ z, const float* __restrict__ hhat,
+                               int grp, int lane, int np, const float (&t_r)[K], const float (&a_r)[K],
+                               const int (&on_r)[K], float gam_t, float gam_a, float* __restrict__ t_out,
+                               float* __restrict__ a_out, uint8_t* __restrict__ act_out);
 
 // RHO: the first pick's correlation stays in LDS (NT <= KSMAX column tiles, 16 bytes per lane and
 // tile) and the later picks update it with rho; otherwise every pick recomputes it from the
@@ -319,17 +333,22 @@ __device__ __forceinline__ void argmax_dpp(float& best, int& bestg) {
 // Workgroup size: 1024 threads when the grid table is copied to LDS without the per-wave
 // correlation tiles (one copy per 16 waves instead of per 4, so fewer workgroups read the same
 // table lines from L2 at the same moment), else 256.
-template <bool EBL, bool RHO, int KSMAX> constexpr int kInitThreads = (EBL && !RHO && KSMAX <= 8) ? 1024 : 256;
+// With the fused data step (DS) and several points, 1024 threads would leave too few registers.
+template <bool EBL, bool RHO, int KSMAX, int K, bool DS>
+constexpr int kInitThreads = (EBL && !RHO && KSMAX <= 8 && (!DS || K == 1)) ? 1024 : 256;
 
-template <int K, int KSMAX, bool RHO, bool EBL>
-__global__ __launch_bounds__((kInitThreads<EBL, RHO, KSMAX>)) void init_kernel(const float* __restrict__ z, const int32_t* __restrict__ n,
+// DS: the iteration's first data step follows in the same launch (srt3d_reconstruct), on the
+// state the plain form writes, with the step sizes every wave derives as init's first workgroup
+// stores them; the result is that of init followed by the stand-alone data step, bit for bit.
+template <int K, int KSMAX, bool RHO, bool EBL, bool DS>
+__global__ __launch_bounds__((kInitThreads<EBL, RHO, KSMAX, K, DS>)) void init_kernel(const float* __restrict__ z, const int32_t* __restrict__ n,
                                                    const float* __restrict__ hhat, float* __restrict__ scal,
                                                    const float* __restrict__ EB, const float* __restrict__ rho, int P,
                                                    int T, int m, int stride, int G, int KS, int NT, float r_min,
                                                    float* __restrict__ t_out, float* __restrict__ a_out,
                                                    uint8_t* __restrict__ act_out,
                                                    const int* __restrict__ nmax_part, int nparts, float eta_t,
-                                                   float eta_a) {
+                                                   float eta_a, const IterArgs A) {
     __shared__ float s_rho[RHO ? 16 * KSMAX : 1];
     __shared__ v4f s_C[RHO ? 4 * KSMAX * 64 : 1];     // [wave][column tile][lane]
     extern __shared__ float4 s_eb4[];                 // EBL: the grid table
@@ -367,6 +386,13 @@ __global__ __launch_bounds__((kInitThreads<EBL, RHO, KSMAX>)) void init_kernel(c
     const int l_first = kq / 2 + 1;                    // harmonic of ks = 0; +2 per ks
     // Loads are unconditional (clamped indices, unused entries zeroed afterwards), so that all of
     // a group's are in flight together rather than each waited for under its own branch.
+    float gam_t = 0.f, gam_a = 0.f;                    // DS: the step sizes of eq. (8)
+    if constexpr (DS) {
+        int v = 0;
+        for (int i = lane; i < nparts; i += 64) v = max(v, nmax_part[i]);
+        for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+        step_sizes(v, K, eta_t, eta_a, scal, gam_t, gam_a);
+    }
     float2 hl[KSMAX];
 #pragma unroll
     for (int ks = 0; ks < KSMAX; ++ks) {
@@ -511,18 +537,36 @@ __global__ __launch_bounds__((kInitThreads<EBL, RHO, KSMAX>)) void init_kernel(c
                 }
             }
         }
-        if (kq == 0 && rv) {
+        if constexpr (!DS) {
+            if (kq == 0 && rv) {
+                bool all[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) all[k] = true;
+                project_capped_simplex<K>(amp_mine, all);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const bool on = np > 0 && (float)np * amp_mine[k] >= r_min;
+                    t_out[(int64_t)prow * K + k] = (float)tau_mine[k];
+                    a_out[(int64_t)prow * K + k] = on ? amp_mine[k] : 0.f;
+                    act_out[(int64_t)prow * K + k] = on ? 1 : 0;
+                }
+            }
+        } else {
+            // every lane forms its row's state (the four lanes of a row hold the same picks)
             bool all[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) all[k] = true;
             project_capped_simplex<K>(amp_mine, all);
+            float t_r[K], a_r[K];
+            int on_r[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const bool on = np > 0 && (float)np * amp_mine[k] >= r_min;
-                t_out[(int64_t)prow * K + k] = (float)tau_mine[k];
-                a_out[(int64_t)prow * K + k] = on ? amp_mine[k] : 0.f;
-                act_out[(int64_t)prow * K + k] = on ? 1 : 0;
+                t_r[k] = (float)tau_mine[k];
+                a_r[k] = on ? amp_mine[k] : 0.f;
+                on_r[k] = on ? 1 : 0;
             }
+            init_data_step<K>(A, z, hhat, grp, lane, np, t_r, a_r, on_r, gam_t, gam_a, t_out, a_out, act_out);
         }
     }
     if (blockIdx.x == 0 && wv == 0) {                  // n_max and the step sizes (eq. 8)
@@ -698,6 +742,46 @@ __global__ __launch_bounds__(256) void data_step_kernel(IterArgs A, const float*
     for (int k = 0; k < K; ++k) {
         t[(int64_t)pix * K + k] = tk[k];
         alpha[(int64_t)pix * K + k] = ak[k];
+    }
+}
+
+// The group's 16 pixels move from init's layout (row r of the product in lanes r, r + 16, r + 32,
+// r + 48) to the data step's (pixel q in the aligned quad 4q .. 4q + 3), then take the same data
+// step as data_step_kernel on the same values: the state as init stores it and the count, sketch
+// and spectrum slices from memory.
+template <int K>
+__device__ void init_data_step(const IterArgs& A, const float* __restrict__ z, const float* __restrict__ hhat,
+                               int grp, int lane, int np, const float (&t_r)[K], const float (&a_r)[K],
+                               const int (&on_r)[K], float gam_t, float gam_a, float* __restrict__ t_out,
+                               float* __restrict__ a_out, uint8_t* __restrict__ act_out) {
+    const int q = lane >> 2, sub = lane & 3;           // lane q (its product row q) holds pixel q's state
+    float tk[K], ak[K];
+    bool on[K];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        tk[k] = __shfl(t_r[k], q, 64);
+        ak[k] = __shfl(a_r[k], q, 64);
+        on[k] = __shfl(on_r[k], q, 64) != 0;
+        any |= on[k];
+    }
+    const float nq = (float)__shfl(np, q, 64);
+    const int pix = grp * 16 + q;
+    const bool pv = pix < A.P;                          // the same for the four lanes of a quad
+    const float2* zrow = reinterpret_cast<const float2*>(z + (int64_t)(pv ? pix : A.P - 1) * 2 * A.m);
+    const float2* hh = reinterpret_cast<const float2*>(hhat);
+    if (any && pv) {                                    // slices read where used: fewer live registers
+        const GlobalSketch src{zrow, hh};
+        data_point<K, kMaxSlice>(src, sub, A.m, A.T, A.invT, A.twoinvT, nq, gam_t, gam_a, tk, ak, on);
+    }
+    if (sub == 0 && pv) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int64_t o = (int64_t)pix * K + k;
+            t_out[o] = tk[k];
+            a_out[o] = ak[k];
+            act_out[o] = on[k] ? 1 : 0;
+        }
     }
 }
 
@@ -2296,7 +2380,7 @@ size_t init_ws_bytes(const srt3d_params& p) {
     }
 
 hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int irf_len, int irf_origin,
-                       const srt3d_params& p, const srt3d_state& st, void* ws, hipStream_t s) {
+                       const srt3d_params& p, const srt3d_state& st, void* ws, hipStream_t s, bool ds) {
     const int P = p.rows * p.cols;
     const InitGrid g = init_grid(p);
     int* part = reinterpret_cast<int*>(ws);
@@ -2317,16 +2401,23 @@ hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int 
     int cus = 0;
     if ((e = current_device_cus(&cus)) != hipSuccess) return e;
     const int64_t groups = ((int64_t)P + 15) / 16;            // 16 pixels per wave
-#define SRT3D_INIT(KSM, RH, EBL)                                                                                  \
+    const IterArgs A = make_args(p);                           // 1 / T and 2 / T for the fused data step
+// one launch of init_kernel<KK, ...> (KK from SRT3D_BY_K): its workgroup size, then the grid
+#define SRT3D_INIT_LAUNCH(KSM, RH, EBL, DS)                                                                       \
     {                                                                                                             \
-        constexpr int TH = kInitThreads<EBL, RH, KSM>;                                                                \
+        constexpr int TH = kInitThreads<EBL, RH, KSM, KK, DS>;                                                    \
         int64_t blocks = (groups + TH / 64 - 1) / (TH / 64);                                                      \
         const int64_t cap = std::min<int64_t>((int64_t)cus * (8 * 256 / TH), kInitBlocksMax);                      \
         if (blocks > cap) blocks = cap;                                                                           \
-        SRT3D_BY_K(p.K_max, hipLaunchKernelGGL((init_kernel<KK, KSM, RH, EBL>), dim3((unsigned)blocks), dim3(TH),   \
-                                               EBL ? (size_t)tab * sizeof(float) : 0, s, z, n, st.hhat, st.scal, EB, \
-                                               rho, P, p.T, p.m, g.stride, g.G, g.KS, g.NT, p.r_min, st.t[0],        \
-                                               st.alpha[0], st.active[0], part, nparts, p.eta_t, p.eta_a))          \
+        hipLaunchKernelGGL((init_kernel<KK, KSM, RH, EBL, DS>), dim3((unsigned)blocks), dim3(TH),                  \
+                           EBL ? (size_t)tab * sizeof(float) : 0, s, z, n, st.hhat, st.scal, EB, rho, P, p.T, p.m,  \
+                           g.stride, g.G, g.KS, g.NT, p.r_min, st.t[0], st.alpha[0], st.active[0], part, nparts,     \
+                           p.eta_t, p.eta_a, A);                                                                  \
+    }
+#define SRT3D_INIT(KSM, RH, EBL)                                                                                  \
+    {                                                                                                             \
+        if (ds) { SRT3D_BY_K(p.K_max, SRT3D_INIT_LAUNCH(KSM, RH, EBL, true)); }                                    \
+        else { SRT3D_BY_K(p.K_max, SRT3D_INIT_LAUNCH(KSM, RH, EBL, false)); }                                      \
     }
     const int ksn = g.KS > g.NT ? g.KS : g.NT;     // with the correlation kept, tiles index registers too
     // without the kept correlation, a grid table of up to 32 KB is read from LDS
@@ -2339,6 +2430,7 @@ hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int 
     else if (g.KS <= 16) { if (ebl) { SRT3D_INIT(16, false, true); } else { SRT3D_INIT(16, false, false); } }
     else { SRT3D_INIT(32, false, false); }
 #undef SRT3D_INIT
+#undef SRT3D_INIT_LAUNCH
     return hipGetLastError();
 }
 

@@ -108,6 +108,39 @@ def test_init_matches_oracle(make):
     np.testing.assert_allclose(g.alpha[same_t], r.alpha[same_t], atol=2e-5)
 
 
+# ----------------------------------------------------------------------------- fused first data step
+def births(dev, **pk):
+    spec = synth.FrameSpec(32, 32, 153, 2.0, 200.0, 2.0, 2, seed=11)
+    return Frame(spec, 10, 2, dev, birth_every=10, r_min=5.0, **pk)
+
+
+def m48(dev, **pk):
+    spec = synth.FrameSpec(20, 24, 4096, 6.0, 300.0, 1.0, 2, seed=55)
+    return Frame(spec, 48, 2, dev, **pk)
+
+
+@pytest.mark.parametrize("make", [tiny, layered, wide, births, m48])
+def test_reconstruct_equals_init_iterate_finalize(make):
+    """srt3d_reconstruct runs the iterations' first data step inside the init launch; its outputs
+    and final state must be those of srt3d_init, srt3d_iterate and srt3d_finalize called one by
+    one, bit for bit (one and several points, the kept-correlation and 1024-thread init forms,
+    merge/birth stages, and m > 32)."""
+    dev = device()
+    fr = make(dev)
+    _case(test="fused_first_step", P=fr.spec.P, K=fr.K, m=fr.m)
+    out = fr.rec.reconstruct(fr.z, fr.n, fr.irf, fr.f.irf_origin)
+    fused = [t.clone() for t in fr.rec.state()]
+    fr.rec.init(fr.z, fr.n, fr.irf, fr.f.irf_origin)
+    fr.rec.iterate(fr.z, fr.n, fr.params.iters)
+    out2 = fr.rec.finalize(fr.n)
+    torch.cuda.synchronize()
+    for k in out:
+        assert torch.equal(out[k], out2[k]), k
+    for a, b in zip(fused, fr.rec.state()):
+        assert torch.equal(a, b)
+    assert int(out["active"].sum()) > 0
+
+
 # ----------------------------------------------------------------------------- one stage at a time
 def _prepared_state(fr, data_steps=2):
     st = O.init_points(fr.zc, fr.nn, fr.hhat, fr.op)
