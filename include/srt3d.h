@@ -272,7 +272,8 @@ int srt3d_sketch_from_hist(const uint16_t* d_hist, int32_t P, int32_t T, int32_t
  *   points per pixel sorted by depth with inactive slots last:
  *   d_depth, d_intensity float32 [P][K_max] (bins; photons n alpha), d_active uint8 [P][K_max],
  *   d_bg float32 [P] (photons per bin).  Any output pointer may be NULL to skip it.
- * srt3d_reconstruct: init + iterate(p->iters) + finalize.
+ * srt3d_reconstruct: init + iterate(p->iters) + finalize, with the same result bit for bit; the
+ *   iterations' first data step runs inside the initialisation's launch.
  * Constraints: rows, cols >= 1, 1 <= m <= SRT3D_MAX_M_RECON, m <= T/2, T * 8 <= 65536,
  * 1 <= K_max <= SRT3D_MAX_K, 0 <= R <= SRT3D_MAX_R, 0 <= Rb <= 8, irf_len >= 1,
  * 0 <= irf_origin < irf_len, iters >= 0, eta_t, eta_a >= 0, birth_every >= 0.
