@@ -2414,11 +2414,21 @@ hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int 
                            g.stride, g.G, g.KS, g.NT, p.r_min, st.t[0], st.alpha[0], st.active[0], part, nparts,     \
                            p.eta_t, p.eta_a, A);                                                                  \
     }
+// The data step runs inside init only for one point per pixel with the grid table in LDS (the
+// 1024-thread forms): there it saves a launch; the other forms hold too many registers already
+// (fewer waves, and the step's sketch reads then wait in turn), so they are followed by the
+// stand-alone data step instead -- the same state either way.
 #define SRT3D_INIT(KSM, RH, EBL)                                                                                  \
-    {                                                                                                             \
-        if (ds) { SRT3D_BY_K(p.K_max, SRT3D_INIT_LAUNCH(KSM, RH, EBL, true)); }                                    \
-        else { SRT3D_BY_K(p.K_max, SRT3D_INIT_LAUNCH(KSM, RH, EBL, false)); }                                      \
-    }
+    SRT3D_BY_K(p.K_max, {                                                                                         \
+        if constexpr (KK == 1 && EBL && !RH && KSM <= 8) {                                                        \
+            if (ds) SRT3D_INIT_LAUNCH(KSM, RH, EBL, true)                                                         \
+            else SRT3D_INIT_LAUNCH(KSM, RH, EBL, false)                                                           \
+        } else {                                                                                                  \
+            SRT3D_INIT_LAUNCH(KSM, RH, EBL, false)                                                                \
+            separate = ds;                                                                                        \
+        }                                                                                                         \
+    })
+    bool separate = false;                          // ds, not fused: the stand-alone data step follows
     const int ksn = g.KS > g.NT ? g.KS : g.NT;     // with the correlation kept, tiles index registers too
     // without the kept correlation, a grid table of up to 32 KB is read from LDS
     const bool ebl = (size_t)tab * sizeof(float) <= kInitTableLds;
@@ -2431,7 +2441,8 @@ hipError_t launch_init(const float* z, const int32_t* n, const double* irf, int 
     else { SRT3D_INIT(32, false, false); }
 #undef SRT3D_INIT
 #undef SRT3D_INIT_LAUNCH
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return separate ? launch_data_step(p, z, n, st, 0, s) : hipSuccess;
 }
 
 hipError_t launch_data_step(const srt3d_params& p, const float* z, const int32_t* n, const srt3d_state& st,
