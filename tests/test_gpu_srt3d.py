@@ -141,6 +141,27 @@ def test_reconstruct_equals_init_iterate_finalize(make):
     assert int(out["active"].sum()) > 0
 
 
+@pytest.mark.parametrize("iters", [0, 1, 2])
+@pytest.mark.parametrize("make", [tiny, births])
+def test_reconstruct_equals_stages_few_iterations(make, iters):
+    """The same equality for runs of 0 (no data step: init is not fused), 1 (the fused step, then
+    one iteration without a next data step) and 2 iterations, on the fused (one point) and the
+    separate (two points) init routes."""
+    dev = device()
+    fr = make(dev, iters=iters)
+    _case(test="fused_first_step_short", P=fr.spec.P, K=fr.K, iters=iters)
+    out = fr.rec.reconstruct(fr.z, fr.n, fr.irf, fr.f.irf_origin)
+    fused = [t.clone() for t in fr.rec.state()]
+    fr.rec.init(fr.z, fr.n, fr.irf, fr.f.irf_origin)
+    fr.rec.iterate(fr.z, fr.n, iters)
+    out2 = fr.rec.finalize(fr.n)
+    torch.cuda.synchronize()
+    for k in out:
+        assert torch.equal(out[k], out2[k]), k
+    for a, b in zip(fused, fr.rec.state()):
+        assert torch.equal(a, b)
+
+
 # ----------------------------------------------------------------------------- one stage at a time
 def _prepared_state(fr, data_steps=2):
     st = O.init_points(fr.zc, fr.nn, fr.hhat, fr.op)
